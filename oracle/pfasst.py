@@ -1,0 +1,149 @@
+"""Two-level PFASST on a block of time steps (oracle; test infrastructure).
+
+Sec. 5.2: n_ts time steps (one per "processor" P_n) are solved together.
+Sec. 5.2.1 (prediction): P_0 sends the initial condition to all; each P_n
+restricts it and performs n+1 coarse sweeps, receiving before each sweep (after
+the first) the last-node value of P_{n-1}; the coarse result is interpolated
+to the fine level and the fine F is re-evaluated at all nodes.
+Sec. 5.2.2, Algorithm alg:pfasst_iteration, per iteration:
+  A) fine sweep; stop here on the last iteration; send the fine last-node value;
+  B) restrict the fine solution to all coarse nodes, evaluate coarse F there,
+     save copies (tilde) and compute tau_c;
+  C) receive the coarse initial condition from P_{n-1}, re-evaluate the coarse
+     F at node 0, coarse FAS sweep, send the coarse last-node value;
+  D) add the interpolated coarse increments of Theta, F_I and F_E at all fine
+     nodes; receive the fine last-node value of P_{n-1}; the new fine initial
+     condition is that value plus the interpolated node-0 coarse increment.
+P_0 skips every receive.
+
+Readings taken where the text is silent or ambiguous:
+  * the fine initial condition received in D is P_{n-1}'s value sent in A of
+    the same iteration (before its own D);
+  * the node-0 coarse increment applied to that received value is the new
+    coarse initial condition minus the restriction of the received value
+    itself.  Taking it against the copy saved in B (the restriction of the
+    old initial condition) would add the low-mode part of the change of the
+    initial condition a second time, on top of the received value that already
+    carries it; that literal form diverges where this one converges to the
+    serial collocation solution (see the PFASST convergence test);
+  * after D the fine F at node 0 is re-evaluated at the new initial condition
+    (the cost model counts this evaluation);
+  * the predictor uses tau = 0, and its final transfer to the fine level adds
+    the interpolated coarse change relative to the restricted initial condition
+    to the spread fine initial condition (so the fine modes the coarse level
+    cannot represent keep their initial values, and P_0 keeps its exact
+    initial condition).
+
+The "processors" are slices of Python lists; every send/receive goes through a
+Mailbox whose receive fails if the message was not sent first, which makes the
+message order of the algorithm explicit and checked.
+"""
+
+import numpy as np
+
+from . import sdc, swe, transfer
+
+
+class Mailbox:
+    def __init__(self):
+        self._box = {}
+
+    def send(self, key, value):
+        if key in self._box:
+            raise RuntimeError(f"message {key} sent twice")
+        self._box[key] = np.array(value, copy=True)
+
+    def recv(self, key):
+        if key not in self._box:
+            raise RuntimeError(f"message {key} received before it was sent")
+        return self._box[key].copy()
+
+
+class PfasstResult:
+    def __init__(self):
+        self.theta = None          # [n_ts][Mf+1, 3, Kf] final fine solution
+        self.end_values = []       # per iteration: [n_ts, 3, Kf] fine last-node values after step A
+        self.pred_end = None       # [n_ts, 3, Kf] fine last-node values after the predictor
+
+
+def _eval_all(lv, th, lin):
+    fe = np.empty_like(th)
+    fi = np.empty_like(th)
+    for i in range(th.shape[0]):
+        fe[i], fi[i] = swe.rhs(lv, th[i], lin)
+    return fe, fi
+
+
+def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False):
+    """PFASST(n_ts, Mf+1, Mc+1, n_iter) over one block starting at theta0 [3, Kf]."""
+    Tf, Tc = lv_f.T, lv_c.T
+    lin = linear_coriolis
+    mb = Mailbox()
+    res = PfasstResult()
+
+    # ---------------------------------------------------------- prediction
+    for n in range(1, n_ts):
+        mb.send(("bcast", n), theta0)
+    ic = [theta0.copy()] + [mb.recv(("bcast", n)) for n in range(1, n_ts)]
+    th_c, fe_c, fi_c, base_c, th_f = [], [], [], [], []
+    for n in range(n_ts):
+        rc = transfer.truncate(ic[n], Tf, Tc)
+        t, e, i = sdc.spread(lv_c, rc, sd_c.M + 1, lin)
+        th_c.append(t); fe_c.append(e); fi_c.append(i)
+        base_c.append(t.copy())
+        th_f.append(np.repeat(ic[n][None], sd_f.M + 1, axis=0))
+    for stage in range(n_ts):
+        for n in range(stage, n_ts):
+            if stage >= 1 and n >= 1:
+                new_ic = mb.recv(("pred", stage - 1, n - 1))
+                th_c[n][0] = new_ic
+                fe_c[n][0], fi_c[n][0] = swe.rhs(lv_c, new_ic, lin)
+            th_c[n], fe_c[n], fi_c[n] = sdc.sweep(lv_c, sd_c, dt, th_c[n], fe_c[n], fi_c[n], None, lin)
+        for n in range(stage, n_ts):
+            mb.send(("pred", stage, n), th_c[n][-1])
+    fe_f, fi_f = [], []
+    for n in range(n_ts):
+        th_f[n] = th_f[n] + transfer.interpolate(sd_c, sd_f, Tc, Tf, th_c[n] - base_c[n])
+        e, i = _eval_all(lv_f, th_f[n], lin)
+        fe_f.append(e); fi_f.append(i)
+    res.pred_end = np.array([th_f[n][-1] for n in range(n_ts)])
+
+    # ----------------------------------------------------------- iterations
+    for k in range(n_iter):
+        # A) fine sweeps
+        for n in range(n_ts):
+            th_f[n], fe_f[n], fi_f[n] = sdc.sweep(lv_f, sd_f, dt, th_f[n], fe_f[n], fi_f[n], None, lin)
+        res.end_values.append(np.array([th_f[n][-1] for n in range(n_ts)]))
+        if k == n_iter - 1:
+            break
+        for n in range(n_ts - 1):
+            mb.send(("fine", k, n), th_f[n][-1])
+        # B) restrict, evaluate, save, tau
+        tilde_th, tilde_fe, tilde_fi, tau = [], [], [], []
+        for n in range(n_ts):
+            th_c[n] = transfer.restrict(sd_f, sd_c, Tf, Tc, th_f[n])
+            fe_c[n], fi_c[n] = _eval_all(lv_c, th_c[n], lin)
+            tilde_th.append(th_c[n].copy()); tilde_fe.append(fe_c[n].copy()); tilde_fi.append(fi_c[n].copy())
+            tau.append(transfer.fas_tau(sd_f, sd_c, Tf, Tc, dt, fe_f[n], fi_f[n], fe_c[n], fi_c[n]))
+        # C) serial coarse chain
+        for n in range(n_ts):
+            if n >= 1:
+                new_ic = mb.recv(("coarse", k, n - 1))
+                th_c[n][0] = new_ic
+                fe_c[n][0], fi_c[n][0] = swe.rhs(lv_c, new_ic, lin)
+            th_c[n], fe_c[n], fi_c[n] = sdc.sweep(lv_c, sd_c, dt, th_c[n], fe_c[n], fi_c[n], tau[n], lin)
+            if n < n_ts - 1:
+                mb.send(("coarse", k, n), th_c[n][-1])
+        # D) interpolate increments, new fine initial condition
+        for n in range(n_ts):
+            d_th = transfer.interpolate(sd_c, sd_f, Tc, Tf, th_c[n] - tilde_th[n])
+            th_f[n] = th_f[n] + d_th
+            fe_f[n] = fe_f[n] + transfer.interpolate(sd_c, sd_f, Tc, Tf, fe_c[n] - tilde_fe[n])
+            fi_f[n] = fi_f[n] + transfer.interpolate(sd_c, sd_f, Tc, Tf, fi_c[n] - tilde_fi[n])
+            if n >= 1:
+                rcv = mb.recv(("fine", k, n - 1))
+                inc0 = transfer.zero_pad(th_c[n][0] - transfer.truncate(rcv, Tf, Tc), Tc, Tf)
+                th_f[n][0] = rcv + inc0
+            fe_f[n][0], fi_f[n][0] = swe.rhs(lv_f, th_f[n][0], lin)
+    res.theta = th_f
+    return res
