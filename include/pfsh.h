@@ -1,0 +1,218 @@
+/*
+ * pfsh.h -- C ABI of the MI355X (gfx950) hot path of PFASST-SH: the IMEX SDC
+ * sweep of the rotating shallow-water equations in a spherical-harmonic basis
+ * (Hamon, Schreiber & Minion, "Parallel-in-Time Multi-Level Integration of the
+ * Shallow-Water Equations on the Rotating Sphere").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Truncation T (triangular): zonal wavenumber m = 0..T, total wavenumber
+ * n = m..T; K = (T+1)(T+2)/2 coefficients per field, stored m-major
+ * (slot of (m,n) = m(T+1) - m(m-1)/2 + (n-m)).  Only m >= 0 is stored: the
+ * fields are real, so the m<0 coefficients are conjugates and Im of every m=0
+ * coefficient is 0 (Sec. 3).  Legendre functions are normalized to
+ * int_{-1}^{1} (P_n^m)^2 dmu = 1 with P_m^m > 0.
+ *
+ * Spectral arrays are complex128, real and imaginary parts interleaved.
+ *   state       [batch][3][K]            variables (Phi, zeta, delta)  (Sec. 2)
+ *   space-time  [batch][n_nodes][3][K]   SDC nodes 0..M               (Sec. 5.1.1)
+ * Grid arrays are float64 [field][nlat][nlon]: Gaussian latitudes from north to
+ * south (mu = sin(latitude) descending), longitudes lambda_k = 2 pi k/nlon.
+ *
+ * Ownership: every array argument is a DEVICE pointer owned by the caller
+ * (allocated e.g. through PyTorch) unless it is marked "host".  A level owns its
+ * tables and its workspace, sized by max_batch at creation; no call allocates
+ * device memory after creation (pfsh_pfasst_create allocates its own buffers).
+ *
+ * Asynchrony and errors: every compute call only enqueues kernels on `stream`
+ * (a hipStream_t passed as void*; NULL = the null stream) and returns at once.
+ * Arguments are validated on the host before anything is enqueued; a rejected
+ * call enqueues nothing.  Launch failures are reported as PFSH_EHIP.  Nothing
+ * throws across the ABI.  One level object may be used by one stream at a time
+ * (its workspace is shared by all of its calls).
+ */
+#ifndef PFSH_H
+#define PFSH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PFSH_OK = 0,
+  PFSH_EINVAL = -1,       /* null pointer, bad scalar argument */
+  PFSH_ESHAPE = -2,       /* sizes inconsistent (batch > max_batch, grid too coarse, ...) */
+  PFSH_ENOMEM = -3,       /* device allocation failed at creation */
+  PFSH_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+  PFSH_EUNSUPPORTED = -5, /* valid but not implemented (e.g. nlon not 2^a or 3*2^a)     */
+  PFSH_ENONFINITE = -6    /* a NaN/Inf was found (pfsh_check_finite) */
+} pfsh_status;
+
+/* Arithmetic of the transform stages (Legendre contractions, ring FFTs, grid
+ * products).  The spectral pre/post steps, the implicit solve, the SDC
+ * accumulation, the residual and the transfers are FP64 in every mode. */
+typedef enum {
+  PFSH_FP64 = 0,   /* FP64 tables and data, FP64 MFMA                        */
+  PFSH_FP32 = 1,   /* FP32 tables and data, FP32 MFMA, FP32 accumulate       */
+  PFSH_BF16X3 = 2  /* x = hi + lo with hi = bf16(x), lo = bf16(x - hi) for
+                      table and data; products hi*hi + hi*lo + lo*hi on BF16
+                      MFMA with FP32 accumulate; FFT and products in FP32     */
+} pfsh_precision;
+
+/* One space-time level of the hierarchy (Sec. 5.3). */
+typedef struct {
+  int T;          /* triangular truncation (largest wavenumber), 1 <= T <= 767         */
+  int nlat;       /* Gaussian latitudes: even, >= T+2                                  */
+  int nlon;       /* longitudes: >= 2T+2, of the form 2^a or 3*2^a, 16 <= nlon <= 1536 */
+  int n_nodes;    /* Gauss-Lobatto SDC nodes M+1, 2..9 (the paper uses 2, 3 and 5)     */
+  int max_batch;  /* largest batch (time slices x members) any call will use, >= 1     */
+  double radius;  /* sphere radius a [m]                                               */
+  double omega;   /* rotation rate Omega [1/s]; Coriolis f = 2 Omega mu               */
+  double phibar;  /* mean geopotential Phibar [m^2/s^2]                                */
+  double nu;      /* diffusion coefficient nu [m^2/s]                                  */
+  int precision;  /* pfsh_precision of the transform stages                            */
+} pfsh_level_desc;
+
+typedef struct pfsh_level pfsh_level;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* pfsh_status_string(pfsh_status s);
+
+/* Host-only validation of a descriptor (no HIP call).  PFSH_OK if
+ * pfsh_level_create would accept it; PFSH_EINVAL / PFSH_ESHAPE /
+ * PFSH_EUNSUPPORTED otherwise. */
+pfsh_status pfsh_level_desc_check(const pfsh_level_desc* desc);
+
+/* Create a level on `device`: Gaussian grid, normalized Legendre tables up to
+ * degree T+1 (built in 80-bit extended precision on the host, then rounded and
+ * packed in the MFMA operand order of the chosen precision), FFT twiddles, the
+ * SDC matrices Q, qE, qI of Sec. 5.1.1 and a workspace for max_batch.
+ * *out receives the handle (NULL on failure).  Synchronous. */
+pfsh_status pfsh_level_create(const pfsh_level_desc* desc, int device, pfsh_level** out);
+
+/* Free a level (synchronizes its device first).  NULL is a no-op. */
+void pfsh_level_destroy(pfsh_level* level);
+
+/* Host copies of the level's sizes and SDC tables (any pointer may be NULL):
+ * K, n_nodes; nodes[n_nodes] on [0,1]; q, qe, qi as row-major
+ * [n_nodes][n_nodes] matrices (Sec. 5.1.1: integration matrix Q, forward-Euler
+ * qE, qI = U^T of the LU factorization of Q^T restricted to nodes 1..M);
+ * mu[nlat] and w[nlat]: Gaussian latitudes (north to south) and weights. */
+pfsh_status pfsh_level_query(const pfsh_level* level, int* K, int* n_nodes, double* nodes,
+                             double* q, double* qe, double* qi, double* mu, double* w);
+
+/* Scalar SH synthesis (Sec. 3, eq. spectral_to_physical_space):
+ * spec [nfields][K] complex128 -> grid [nfields][nlat][nlon] float64,
+ * xi(lambda_k, mu_j) = sum_{m,n} xi_n^m P_n^m(mu_j) e^{i m lambda_k} (m<0 terms by
+ * conjugation).  1 <= nfields <= 4*max_batch. */
+pfsh_status pfsh_sh_synthesis(pfsh_level* level, const void* spec, void* grid, int nfields,
+                              void* stream);
+
+/* Scalar SH analysis (Sec. 3: Fourier transform in longitude, then Gauss-
+ * Legendre quadrature in latitude): grid [nfields][nlat][nlon] float64 ->
+ * spec [nfields][K] complex128, xi_n^m = sum_j w_j P_n^m(mu_j) X_m(mu_j) with
+ * X_m(mu_j) = (1/nlon) sum_k xi(lambda_k, mu_j) e^{-i m lambda_k}; Im of m = 0
+ * is set to 0.  1 <= nfields <= 5*max_batch. */
+pfsh_status pfsh_sh_analysis(pfsh_level* level, const void* grid, void* spec, int nfields,
+                             void* stream);
+
+/* Right-hand sides at `batch` states (Sec. 2 and 4): f_expl = F_E = N(state),
+ * the nonlinear terms of eq. nonlinear_operators evaluated with the transform
+ * method, and f_impl = F_I = L(state) of eq.
+ * linear_wave_motion_induced_by_gravitational_forces.  All [batch][3][K].
+ * Either output may be NULL to skip it. */
+pfsh_status pfsh_rhs(pfsh_level* level, const void* state, void* f_expl, void* f_impl, int batch,
+                     void* stream);
+
+/* Implicit solve of Sec. 5.4: x = (I - beta L)^{-1} b per mode (a 2x2 system
+ * for (Phi, delta) and a scalar one for zeta).  b, x: [batch][3][K]; x may
+ * equal b (in place).  beta >= 0. */
+pfsh_status pfsh_implicit_solve(pfsh_level* level, double beta, const void* b, void* x, int batch,
+                                void* stream);
+
+/* One IMEX SDC sweep (Sec. 5.1.1, eq. update_equation_sdcq_discrete_form; with
+ * tau != NULL the FAS form eq. modified_update_equation_sdcq_discrete_form).
+ * theta, f_expl, f_impl, tau: [batch][n_nodes][3][K].  On entry node 0 holds
+ * the initial condition and its F_E, F_I (already evaluated there); nodes
+ * 1..M hold the previous iterate.  On return nodes 1..M hold the new iterate
+ * and its F_E, F_I; node 0 is not touched.  dt > 0. */
+pfsh_status pfsh_sdc_sweep(pfsh_level* level, double dt, void* theta, void* f_expl, void* f_impl,
+                           const void* tau, int batch, void* stream);
+
+/* Collocation residual (Sec. 5.1.1, eq. collocation_problem; FAS form of
+ * Sec. 5.1.2 when tau != NULL): r^m = theta^0 + dt (Q F)_m + tau^m - theta^m.
+ * out [batch][3] float64 (device) receives max over nodes and modes of |r|
+ * per slice and variable; a NaN/Inf anywhere gives NaN in that entry. */
+pfsh_status pfsh_residual(pfsh_level* level, double dt, const void* theta, const void* f_expl,
+                          const void* f_impl, const void* tau, double* out, int batch, void* stream);
+
+/* Synchronous check of a [count] float64 device array: PFSH_ENONFINITE if any
+ * entry is NaN/Inf, PFSH_OK otherwise (waits for `stream`). */
+pfsh_status pfsh_check_finite(const double* values, int count, void* stream);
+
+/* Copy node 0 of theta, f_expl, f_impl to every node ("spread" initial iterate;
+ * any array may be NULL).  [batch][n_nodes][3][K]. */
+pfsh_status pfsh_spread(pfsh_level* level, void* theta, void* f_expl, void* f_impl, int batch,
+                        void* stream);
+
+/* Restriction R = (R^s)(R^t) of Sec. 5.3 (eq. time_restriction then
+ * eq. space_restriction): in_f [batch][Mf+1][3][Kf] -> out_c [batch][Mc+1][3][Kc];
+ * temporal Lagrange interpolation from fine to coarse nodes (pointwise
+ * injection for nested Lobatto sets), then truncation to m, n <= Tc. */
+pfsh_status pfsh_restrict(const pfsh_level* fine, const pfsh_level* coarse, const void* in_f,
+                          void* out_c, int batch, void* stream);
+
+/* Interpolation P = (P^t)(P^s) of Sec. 5.3 applied to a coarse increment and
+ * added: inout_f += P (new_c - old_c) (old_c may be NULL for P new_c); zero-
+ * padding in space, Lagrange interpolation from coarse to fine nodes.
+ * new_c, old_c [batch][Mc+1][3][Kc]; inout_f [batch][Mf+1][3][Kf]. */
+pfsh_status pfsh_interpolate_add(const pfsh_level* coarse, const pfsh_level* fine, const void* new_c,
+                                 const void* old_c, void* inout_f, int batch, void* stream);
+
+/* FAS correction of Sec. 5.1.2 (eq. tau_term_level_l+1 with tau_f = 0):
+ * tau_c = dt [ R (Q_f (x) I) F_f - (Q_c (x) I) F_c ], where F_c must be the coarse
+ * F at R theta_f.  fe_f, fi_f [batch][Mf+1][3][Kf]; fe_c, fi_c, tau_c
+ * [batch][Mc+1][3][Kc]. */
+pfsh_status pfsh_fas_tau(const pfsh_level* fine, const pfsh_level* coarse, double dt,
+                         const void* fe_f, const void* fi_f, const void* fe_c, const void* fi_c,
+                         void* tau_c, int batch, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Two-level PFASST on one device (Sec. 5.2).  The n_ts time steps of a block
+ * ("processors" P_0..P_{n_ts-1}) and `members` independent ensemble members
+ * are one batch: slice index s = step * members + member, so a step's members
+ * are contiguous.  The send/receive of Algorithm 1 become device copies along
+ * the batch axis; the coarse step C stays a serial chain over steps.
+ * Fine arrays theta_f, fe_f, fi_f: [n_ts*members][Mf+1][3][Kf], owned by the
+ * caller.  The context owns the coarse arrays, saved copies, tau and the
+ * last-node snapshots (allocated at creation).
+ * ------------------------------------------------------------------------- */
+typedef struct pfsh_pfasst pfsh_pfasst;
+
+/* fine->max_batch and coarse->max_batch must be >= n_ts*members. */
+pfsh_status pfsh_pfasst_create(pfsh_level* fine, pfsh_level* coarse, int n_ts, int members,
+                               pfsh_pfasst** out);
+void pfsh_pfasst_destroy(pfsh_pfasst* ctx);
+
+/* Prediction (Sec. 5.2.1) from theta0 [members][3][Kf]: broadcast, restrict,
+ * n_ts wavefront stages of coarse sweeps (stage j sweeps steps j..n_ts-1, step
+ * n >= 1 taking the stage-(j-1) last-node value of step n-1 as its initial
+ * condition), then fine = spread(theta0) + P(coarse - R spread(theta0)) and
+ * fine F at all nodes.  Writes theta_f, fe_f, fi_f. */
+pfsh_status pfsh_pfasst_predict(pfsh_pfasst* ctx, double dt, const void* theta0, void* theta_f,
+                                void* fe_f, void* fi_f, void* stream);
+
+/* One PFASST iteration (Sec. 5.2.2, Algorithm 1): A) batched fine sweep; if
+ * `last` != 0 stop here; B) restrict, coarse F at all nodes, saved copies, tau;
+ * C) serial chain over steps: new coarse initial condition from step n-1,
+ * coarse F at node 0, coarse FAS sweep; D) interpolate the coarse increments of
+ * theta, F_E and F_I to all fine nodes, new fine initial condition = fine
+ * last-node value of step n-1 from A plus P(coarse initial condition - R of that
+ * value), fine F at node 0. */
+pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
+                                int last, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFSH_H */

@@ -1,0 +1,353 @@
+// Longitude stage of the transform (Sec. 3, first step) and the grid-point
+// nonlinear products of Sec. 2, one pair of equator-symmetric rings per
+// workgroup, everything resident in LDS.
+//
+// Two real rings are carried as one complex signal (north in the real part,
+// south in the imaginary part), so a length-nlon complex FFT transforms both.
+// The FFT is a self-sorting (Stockham) radix-4/2/3 transform: at every stage
+// each thread reads its butterflies' inputs into registers, the workgroup
+// synchronizes, and the outputs are written back in place.
+//
+// k_ring_rhs: Fourier coefficients of Phi', zeta, U = u cos(phi), V = v cos(phi)
+//   (parity form E/O per m) -> grid -> eta = zeta + 2 Omega mu, A = eta U,
+//   B = eta V, C = Phi' U, D = Phi' V, E = (U^2 + V^2)/2 -> Fourier coefficients
+//   weighted by w_j / ((1 - mu_j^2) nlon), in parity form (north +- south),
+//   written as the analysis data operand.
+// k_ring_synth / k_ring_anal: the same longitude step for scalar fields.
+#include "mfma_ops.h"
+
+namespace pfsh {
+
+template <typename R>
+struct cpx {
+  R x, y;
+};
+template <typename R>
+__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// radix of stage s for a length-N transform: 4s first, then a 2, then a 3
+__host__ __device__ constexpr int radix_of(int N, int s) {
+  int n = N, st = 0;
+  while (n % 4 == 0) { if (st == s) return 4; n /= 4; ++st; }
+  while (n % 2 == 0) { if (st == s) return 2; n /= 2; ++st; }
+  while (n % 3 == 0) { if (st == s) return 3; n /= 3; ++st; }
+  return 0;
+}
+__host__ __device__ constexpr int nstages(int N) {
+  int s = 0;
+  while (radix_of(N, s) != 0) ++s;
+  return s;
+}
+
+template <int RAD, int SIGN, typename R>
+__device__ __forceinline__ void butterfly(cpx<R>* a) {
+  if constexpr (RAD == 2) {
+    cpx<R> t = a[0];
+    a[0] = t + a[1];
+    a[1] = t - a[1];
+  } else if constexpr (RAD == 3) {
+    const R h = (R)0.86602540378443864676;  // sqrt(3)/2
+    cpx<R> t = a[1] + a[2], d = a[1] - a[2];
+    cpx<R> m = {a[0].x - (R)0.5 * t.x, a[0].y - (R)0.5 * t.y};
+    cpx<R> r = {-(R)SIGN * h * d.y, (R)SIGN * h * d.x};
+    a[0] = a[0] + t;
+    a[1] = m + r;
+    a[2] = m - r;
+  } else {
+    cpx<R> s02 = a[0] + a[2], d02 = a[0] - a[2], s13 = a[1] + a[3], d13 = a[1] - a[3];
+    cpx<R> jd = {-(R)SIGN * d13.y, (R)SIGN * d13.x};
+    a[0] = s02 + s13;
+    a[1] = d02 + jd;
+    a[2] = s02 - s13;
+    a[3] = d02 - jd;
+  }
+}
+
+// One Stockham stage on NSIG signals of length N stored back to back in buf.
+template <typename R, int N, int RAD, int NSIG, int NT, int SIGN, int NS>
+__device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+  constexpr int NB = N / RAD;
+  constexpr int TOT = NB * NSIG;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int STEP = N / (NS * RAD);
+  cpx<R> v[PER][RAD];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (TOT % NT == 0 || t < TOT) {
+      const int sig = t / NB, j = t - sig * NB, k = j % NS;
+      const cpx<R>* b = buf + sig * N;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[q][r] = b[j + r * NB];
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cpx<R> w = tw[r * k * STEP];
+          if (SIGN < 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      butterfly<RAD, SIGN>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (TOT % NT == 0 || t < TOT) {
+      const int sig = t / NB, j = t - sig * NB, k = j % NS;
+      cpx<R>* b = buf + sig * N + (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) b[r * NS] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int N, int NSIG, int NT, int SIGN, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+  if constexpr (S < nstages(N)) {
+    constexpr int RAD = radix_of(N, S);
+    fft_stage<R, N, RAD, NSIG, NT, SIGN, NS>(buf, tw);
+    fft_run<R, N, NSIG, NT, SIGN, S + 1, NS * RAD>(buf, tw);
+  }
+}
+
+// Write one complex value (re, im at columns c, c+1) of degree-parity p of
+// order m for ring j into the analysis data operand.
+template <class Op>
+__device__ __forceinline__ void put_g(void* G, int kb2, int CBa, int m, int p, int j, int c,
+                                      typename Op::R re, typename Op::R im) {
+  const int KB = Op::KB;
+  const long long blk0 = ((long long)(2 * m + p) * kb2 + j / KB) * CBa;
+  const int k = j % KB;
+  const int e = (Op::KIND == OP_BF16X3) ? (k & 7) : 0;
+  const int lk = (Op::KIND == OP_BF16X3) ? (k >> 3) : k;
+  Op::store(G, blk0 + c / 16, lk * 16 + (c % 16), e, re);
+  const int c1 = c + 1;
+  Op::store(G, blk0 + c1 / 16, lk * 16 + (c1 % 16), e, im);
+}
+
+// Fourier coefficients of a north/south pair from the parity form -> two-for-one
+// complex spectrum (positive exponent synthesis convention).
+template <typename R>
+__device__ __forceinline__ void load_pair(cpx<R>* sig, int N, int m, cpx<R> E, cpx<R> O) {
+  cpx<R> xn = E + O, xs = E - O;
+  if (m == 0) {
+    sig[0] = {xn.x, xs.x};
+  } else {
+    sig[m] = {xn.x - xs.y, xn.y + xs.x};
+    sig[N - m] = {xn.x + xs.y, xs.x - xn.y};
+  }
+}
+
+// Split the forward spectrum of north + i south into the two real spectra.
+template <typename R>
+__device__ __forceinline__ void split_pair(const cpx<R>* sig, int N, int m, cpx<R>& yn,
+                                           cpx<R>& ys) {
+  cpx<R> z = sig[m], w = sig[(N - m) % N];
+  yn = {(R)0.5 * (z.x + w.x), (R)0.5 * (z.y - w.y)};
+  ys = {(R)0.5 * (z.y + w.y), (R)0.5 * (w.x - z.x)};
+}
+
+template <class Op, int N>
+__global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restrict__ F4,
+                                                 void* __restrict__ G,
+                                                 const double* __restrict__ mu,
+                                                 const double* __restrict__ wq,
+                                                 const cpx<typename Op::R>* __restrict__ tw, int J,
+                                                 int L, int kb2, int CBa, double two_omega) {
+  typedef typename Op::R R;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  constexpr int NT = 256;
+  const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int T = L - 1;
+  for (int i = tid; i < 4 * N; i += NT) buf[i] = {(R)0, (R)0};
+  __syncthreads();
+  const R* src = F4 + ((size_t)b * J + j) * 4 * 2 * L * 2;
+  for (int i = tid; i < 4 * L; i += NT) {
+    const int f = i / L, m = i - f * L;
+    const R* e = src + ((f * 2 + 0) * L + m) * 2;
+    const R* o = src + ((f * 2 + 1) * L + m) * 2;
+    load_pair<R>(buf + f * N, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
+  }
+  __syncthreads();
+  fft_run<R, N, 4, NT, +1>(buf, tw);
+  const double muj = mu[j];
+  const R fn = (R)(two_omega * muj), fs = -fn;
+  for (int k = tid; k < N; k += NT) {
+    const cpx<R> ph = buf[k], ze = buf[N + k], u = buf[2 * N + k], v = buf[3 * N + k];
+    const R en = ze.x + fn, es = ze.y + fs;
+    buf[k] = {en * u.x, es * u.y};
+    buf[N + k] = {en * v.x, es * v.y};
+    buf[2 * N + k] = {ph.x * u.x, ph.y * u.y};
+    buf[3 * N + k] = {ph.x * v.x, ph.y * v.y};
+    buf[4 * N + k] = {(R)0.5 * (u.x * u.x + v.x * v.x), (R)0.5 * (u.y * u.y + v.y * v.y)};
+  }
+  __syncthreads();
+  fft_run<R, N, 5, NT, -1>(buf, tw);
+  const R scale = (R)(wq[j] / ((1.0 - muj * muj) * (double)N));
+  for (int i = tid; i < 5 * L; i += NT) {
+    const int m = i / 5, f = i - m * 5;
+    cpx<R> yn, ys;
+    split_pair<R>(buf + f * N, N, m, yn, ys);
+    const int c = (b * 5 + f) * 2;
+    cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
+    cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
+    if (m == 0) { gp.y = 0; gm.y = 0; }
+    put_g<Op>(G, kb2, CBa, m, 0, j, c, gp.x, gp.y);
+    put_g<Op>(G, kb2, CBa, m, 1, j, c, gm.x, gm.y);
+  }
+  (void)T;
+}
+
+// scalar synthesis: F4 [0][j][nf][2][L] -> grid [nf][nlat][N]
+template <class Op, int N>
+__global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __restrict__ F4,
+                                                   double* __restrict__ grid,
+                                                   const cpx<typename Op::R>* __restrict__ tw,
+                                                   int J, int L, int nf) {
+  typedef typename Op::R R;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  constexpr int NT = 256;
+  const int j = blockIdx.x, f0 = blockIdx.y * 4, tid = threadIdx.x;
+  for (int i = tid; i < 4 * N; i += NT) buf[i] = {(R)0, (R)0};
+  __syncthreads();
+  for (int i = tid; i < 4 * L; i += NT) {
+    const int fl = i / L, m = i - fl * L, f = f0 + fl;
+    if (f >= nf) continue;
+    const R* e = F4 + ((((size_t)j * nf + f) * 2 + 0) * L + m) * 2;
+    const R* o = F4 + ((((size_t)j * nf + f) * 2 + 1) * L + m) * 2;
+    load_pair<R>(buf + fl * N, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
+  }
+  __syncthreads();
+  fft_run<R, N, 4, NT, +1>(buf, tw);
+  const int nlat = 2 * J;
+  for (int i = tid; i < 4 * N; i += NT) {
+    const int fl = i / N, k = i - fl * N, f = f0 + fl;
+    if (f >= nf) continue;
+    const cpx<R> z = buf[i];
+    grid[((size_t)f * nlat + j) * N + k] = (double)z.x;
+    grid[((size_t)f * nlat + (nlat - 1 - j)) * N + k] = (double)z.y;
+  }
+}
+
+// scalar analysis: grid [nf][nlat][N] -> analysis data operand, weight w_j / N
+template <class Op, int N>
+__global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ grid,
+                                                  void* __restrict__ G,
+                                                  const double* __restrict__ wq,
+                                                  const cpx<typename Op::R>* __restrict__ tw,
+                                                  int J, int L, int nf, int kb2, int CBa) {
+  typedef typename Op::R R;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  constexpr int NT = 256;
+  const int j = blockIdx.x, f0 = blockIdx.y * 4, tid = threadIdx.x;
+  const int nlat = 2 * J;
+  for (int i = tid; i < 4 * N; i += NT) {
+    const int fl = i / N, k = i - fl * N, f = f0 + fl;
+    cpx<R> z = {(R)0, (R)0};
+    if (f < nf)
+      z = {(R)grid[((size_t)f * nlat + j) * N + k], (R)grid[((size_t)f * nlat + (nlat - 1 - j)) * N + k]};
+    buf[i] = z;
+  }
+  __syncthreads();
+  fft_run<R, N, 4, NT, -1>(buf, tw);
+  const R scale = (R)(wq[j] / (double)N);
+  for (int i = tid; i < 4 * L; i += NT) {
+    const int m = i / 4, fl = i - m * 4, f = f0 + fl;
+    if (f >= nf) continue;
+    cpx<R> yn, ys;
+    split_pair<R>(buf + fl * N, N, m, yn, ys);
+    cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
+    cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
+    if (m == 0) { gp.y = 0; gm.y = 0; }
+    put_g<Op>(G, kb2, CBa, m, 0, j, 2 * f, gp.x, gp.y);
+    put_g<Op>(G, kb2, CBa, m, 1, j, 2 * f, gm.x, gm.y);
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+template <class Op, int N>
+static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const double* gin,
+                              double* gout, hipStream_t s) {
+  typedef typename Op::R R;
+  const cpx<R>* tw = reinterpret_cast<const cpx<R>*>(lv->tw_d);
+  size_t shm;
+  if (kind == 0) {
+    shm = (size_t)5 * N * sizeof(cpx<R>);
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((k_ring_rhs<Op, N>), dim3(lv->J, count), dim3(256), shm, s,
+                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->kb2,
+                       lv->CBa, 2.0 * lv->d.omega);
+  } else if (kind == 1) {
+    shm = (size_t)4 * N * sizeof(cpx<R>);
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)k_ring_synth<Op, N>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((k_ring_synth<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
+                       (const R*)lv->F4, gout, tw, lv->J, lv->L, count);
+  } else {
+    shm = (size_t)4 * N * sizeof(cpx<R>);
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)k_ring_anal<Op, N>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((k_ring_anal<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
+                       gin, lv->G, lv->w_d, tw, lv->J, lv->L, count, lv->kb2, lv->CBa);
+  }
+  return hipGetLastError();
+}
+
+template <class Op>
+static hipError_t ring_by_n(int kind, const pfsh_level* lv, int count, const double* gin,
+                            double* gout, hipStream_t s) {
+  switch (lv->nlon) {
+    case 16: return ring_launch<Op, 16>(kind, lv, count, gin, gout, s);
+    case 24: return ring_launch<Op, 24>(kind, lv, count, gin, gout, s);
+    case 32: return ring_launch<Op, 32>(kind, lv, count, gin, gout, s);
+    case 48: return ring_launch<Op, 48>(kind, lv, count, gin, gout, s);
+    case 64: return ring_launch<Op, 64>(kind, lv, count, gin, gout, s);
+    case 96: return ring_launch<Op, 96>(kind, lv, count, gin, gout, s);
+    case 128: return ring_launch<Op, 128>(kind, lv, count, gin, gout, s);
+    case 192: return ring_launch<Op, 192>(kind, lv, count, gin, gout, s);
+    case 256: return ring_launch<Op, 256>(kind, lv, count, gin, gout, s);
+    case 384: return ring_launch<Op, 384>(kind, lv, count, gin, gout, s);
+    case 512: return ring_launch<Op, 512>(kind, lv, count, gin, gout, s);
+    case 768: return ring_launch<Op, 768>(kind, lv, count, gin, gout, s);
+    case 1024: return ring_launch<Op, 1024>(kind, lv, count, gin, gout, s);
+    case 1536: return ring_launch<Op, 1536>(kind, lv, count, gin, gout, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t ring_dispatch(int kind, const pfsh_level* lv, int count, const double* gin,
+                                double* gout, hipStream_t s) {
+  switch (lv->op) {
+    case OP_F64: return ring_by_n<OpF64>(kind, lv, count, gin, gout, s);
+    case OP_F32: return ring_by_n<OpF32>(kind, lv, count, gin, gout, s);
+    default: return ring_by_n<OpBF3>(kind, lv, count, gin, gout, s);
+  }
+}
+
+hipError_t launch_ring_rhs(const pfsh_level* lv, int batch, hipStream_t s) {
+  return ring_dispatch(0, lv, batch, nullptr, nullptr, s);
+}
+hipError_t launch_ring_synth(const pfsh_level* lv, int nfields, double* grid, hipStream_t s) {
+  return ring_dispatch(1, lv, nfields, nullptr, grid, s);
+}
+hipError_t launch_ring_anal(const pfsh_level* lv, int nfields, const double* grid, hipStream_t s) {
+  return ring_dispatch(2, lv, nfields, grid, nullptr, s);
+}
+
+}  // namespace pfsh

@@ -1,0 +1,763 @@
+// FP64 spectral-space kernels: transform pre/post steps, the linear operator
+// and implicit solve, the SDC sweep accumulation, the collocation residual and
+// the space-time transfers.  All are bandwidth-bound element-wise passes over
+// [batch][...][3][K] complex128 arrays.
+#include "mfma_ops.h"
+
+namespace pfsh {
+
+struct C2 {
+  double x, y;
+};
+__device__ __forceinline__ C2 ld2(const double* p) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void st2(double* p, C2 v) {
+  *reinterpret_cast<double2*>(p) = make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ double eps_nm(int n, int m) {
+  return n > m ? sqrt((double)(n * n - m * m) / (double)(4 * n * n - 1)) : 0.0;
+}
+
+// slot k -> (m, n) of the m-major layout
+__device__ __forceinline__ void slot_mn(int T, int k, int& m, int& n) {
+  const double b = 2.0 * T + 3.0;
+  int mm = (int)((b - sqrt(b * b - 8.0 * k)) * 0.5);
+  if (mm < 0) mm = 0;
+  while (mm > 0 && spec_off(T, mm) > k) --mm;
+  while (mm < T && spec_off(T, mm + 1) <= k) ++mm;
+  m = mm;
+  n = mm + (k - spec_off(T, mm));
+}
+
+struct Phys {
+  double a, omega, phibar, nu;
+};
+
+// -------------------------------------------------------------- RHS prep
+// One workgroup per (m, batch entry).  Writes the synthesis data operand for
+// the four fields Phi', zeta, U, V at degrees n' = m..T+1:
+//   Phi'_n' = Phi_n' (minus sqrt(2) Phibar at (0,0)), zeta_n'      (0 at n' = T+1)
+//   U_n' = (1/a) [ i m chi_n' - psit_n' ],  V_n' = (1/a) [ i m psi_n' + chit_n' ]
+//   psit_n' = -(n'-1) eps_n' psi_{n'-1} + (n'+2) eps_{n'+1} psi_{n'+1}
+// (the H_n^m = (1-mu^2) dP_n^m/dmu terms rewritten on P_{n'}, Sec. 2-3), with
+// psi = -a^2 zeta/(n(n+1)), chi = -a^2 delta/(n(n+1)) (Helmholtz, Sec. 2).
+// Optionally F_I = L(Theta) per mode.
+template <class Op>
+__global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th, long long sstride,
+                                                 double* __restrict__ fi, long long fstride,
+                                                 void* __restrict__ X, const MPInfo* __restrict__ mpi,
+                                                 int T, int CBs, Phys ph) {
+  const int m = blockIdx.x, b = blockIdx.y;
+  const double* P = th + (size_t)b * sstride * 2;
+  const int K = (T + 1) * (T + 2) / 2;
+  const int off = spec_off(T, m);
+  const double ia = 1.0 / ph.a, a2 = ph.a * ph.a;
+  auto psi = [&](const double* base, int n) -> C2 {   // inverse Laplacian of field at (m, n)
+    if (n < m || n > T || n == 0) return {0.0, 0.0};
+    C2 z = ld2(base + 2 * (off + n - m));
+    const double s = -a2 / ((double)n * (n + 1));
+    return {s * z.x, s * z.y};
+  };
+  const double* Pphi = P;
+  const double* Pzeta = P + 2 * K;
+  const double* Pdelta = P + 4 * K;
+  for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
+    C2 phi = {0, 0}, zeta = {0, 0};
+    if (n <= T) {
+      phi = ld2(Pphi + 2 * (off + n - m));
+      zeta = ld2(Pzeta + 2 * (off + n - m));
+      if (fi) {
+        const C2 dl = ld2(Pdelta + 2 * (off + n - m));
+        const double lam = -(double)n * (n + 1) / a2;
+        double* F = fi + (size_t)b * fstride * 2;
+        st2(F + 2 * (off + n - m), {-ph.phibar * dl.x + ph.nu * lam * phi.x,
+                                    -ph.phibar * dl.y + ph.nu * lam * phi.y});
+        st2(F + 2 * (K + off + n - m), {ph.nu * lam * zeta.x, ph.nu * lam * zeta.y});
+        st2(F + 2 * (2 * K + off + n - m), {-lam * phi.x + ph.nu * lam * dl.x,
+                                            -lam * phi.y + ph.nu * lam * dl.y});
+      }
+    }
+    if (n == 0) phi.x -= 1.4142135623730950488 * ph.phibar;
+    const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
+    const C2 ps_m = psi(Pzeta, n - 1), ps_p = psi(Pzeta, n + 1), ps_0 = psi(Pzeta, n);
+    const C2 ch_m = psi(Pdelta, n - 1), ch_p = psi(Pdelta, n + 1), ch_0 = psi(Pdelta, n);
+    const double cm = -(double)(n - 1) * e0, cp = (double)(n + 2) * e1;
+    const C2 pst = {cm * ps_m.x + cp * ps_p.x, cm * ps_m.y + cp * ps_p.y};
+    const C2 cht = {cm * ch_m.x + cp * ch_p.x, cm * ch_m.y + cp * ch_p.y};
+    // i m chi = (-m chi.y, m chi.x)
+    const C2 U = {ia * (-m * ch_0.y - pst.x), ia * (m * ch_0.x - pst.y)};
+    const C2 V = {ia * (-m * ps_0.y + cht.x), ia * (m * ps_0.x + cht.y)};
+    const int p = (n - m) & 1, i = (n - m) >> 1;
+    const MPInfo q = mpi[2 * m + p];
+    const int KB = Op::KB;
+    const long long blk0 = q.xS + (long long)(i / KB) * CBs;
+    const int kk = i % KB;
+    const int e = (Op::KIND == OP_BF16X3) ? (kk & 7) : 0;
+    const int lk = (Op::KIND == OP_BF16X3) ? (kk >> 3) : kk;
+    const C2 vals[4] = {phi, zeta, U, V};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int c = (b * 4 + f) * 2;
+      Op::store(X, blk0 + c / 16, lk * 16 + (c % 16), e, (typename Op::R)vals[f].x);
+      Op::store(X, blk0 + (c + 1) / 16, lk * 16 + ((c + 1) % 16), e, (typename Op::R)vals[f].y);
+    }
+  }
+}
+
+// scalar synthesis input: nfields spectra [f][K] -> operand (degree T+1 = 0)
+template <class Op>
+__global__ __launch_bounds__(128) void k_prep_scalar(const double* __restrict__ spec,
+                                                    void* __restrict__ X,
+                                                    const MPInfo* __restrict__ mpi, int T,
+                                                    int CBs) {
+  const int m = blockIdx.x, f = blockIdx.y;
+  const int K = (T + 1) * (T + 2) / 2, off = spec_off(T, m);
+  for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
+    C2 z = {0, 0};
+    if (n <= T) z = ld2(spec + 2 * ((size_t)f * K + off + n - m));
+    const int p = (n - m) & 1, i = (n - m) >> 1;
+    const MPInfo q = mpi[2 * m + p];
+    const int KB = Op::KB;
+    const long long blk0 = q.xS + (long long)(i / KB) * CBs;
+    const int kk = i % KB;
+    const int e = (Op::KIND == OP_BF16X3) ? (kk & 7) : 0;
+    const int lk = (Op::KIND == OP_BF16X3) ? (kk >> 3) : kk;
+    const int c = 2 * f;
+    Op::store(X, blk0 + c / 16, lk * 16 + (c % 16), e, (typename Op::R)z.x);
+    Op::store(X, blk0 + (c + 1) / 16, lk * 16 + ((c + 1) % 16), e, (typename Op::R)z.y);
+  }
+}
+
+// scalar analysis output: Y [f][Kx] -> spec [f][K], Im of m = 0 set to 0
+template <typename R>
+__global__ void k_unpack_scalar(const R* __restrict__ Y, double* __restrict__ spec, int T,
+                                int nf) {
+  const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
+  const long long tot = (long long)nf * K;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int f = (int)(idx / K), k = (int)(idx - (long long)f * K);
+    int m, n;
+    slot_mn(T, k, m, n);
+    const R* y = Y + 2 * ((size_t)f * Kx + ext_off(T, m) + n - m);
+    st2(spec + 2 * idx, {(double)y[0], m == 0 ? 0.0 : (double)y[1]});
+  }
+}
+
+// -------------------------------------------------------------- assembly
+// F_E from the analysed products (Sec. 2, transform method):
+//   D[X,Y]_n = (1/a) [ i m X_n - ( -n eps_{n+1} Y_{n+1} + (n+1) eps_n Y_{n-1} ) ]
+//   N_zeta = -D[A,B], N_delta = D[B,-A] + n(n+1)/a^2 E_n, N_Phi = -D[C,D]
+// where X_n, Y_n are the weighted P-contractions (degrees to T+1).
+template <typename R>
+__global__ __launch_bounds__(128) void k_assemble(const R* __restrict__ Y, double* __restrict__ fe,
+                                                 long long fstride, int T, double a) {
+  const int m = blockIdx.x, b = blockIdx.y;
+  const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
+  const int eoff = ext_off(T, m), off = spec_off(T, m);
+  const double ia = 1.0 / a;
+  const R* Yb = Y + (size_t)b * 5 * Kx * 2;
+  auto get = [&](int f, int n) -> C2 {
+    if (n < m || n > T + 1) return {0.0, 0.0};
+    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + n - m);
+    return {(double)p[0], (double)p[1]};
+  };
+  double* F = fe + (size_t)b * fstride * 2;
+  for (int n = m + threadIdx.x; n <= T; n += blockDim.x) {
+    const double cp = -(double)n * eps_nm(n + 1, m), cm = (double)(n + 1) * eps_nm(n, m);
+    // H-weighted parts: hY = cp Y_{n+1} + cm Y_{n-1}
+    const C2 An = get(0, n), Bn = get(1, n), Cn = get(2, n), En = get(4, n);
+    const C2 Ap = get(0, n + 1), Am = get(0, n - 1);
+    const C2 Bp = get(1, n + 1), Bm = get(1, n - 1);
+    const C2 Dp = get(3, n + 1), Dm = get(3, n - 1);
+    const C2 hB = {cp * Bp.x + cm * Bm.x, cp * Bp.y + cm * Bm.y};
+    const C2 hA = {cp * Ap.x + cm * Am.x, cp * Ap.y + cm * Am.y};
+    const C2 hD = {cp * Dp.x + cm * Dm.x, cp * Dp.y + cm * Dm.y};
+    // D[X,Y] = (1/a)(i m X - hY);  i m X = (-m X.y, m X.x)
+    const C2 dAB = {ia * (-m * An.y - hB.x), ia * (m * An.x - hB.y)};
+    const C2 dBmA = {ia * (-m * Bn.y + hA.x), ia * (m * Bn.x + hA.y)};
+    const C2 dCD = {ia * (-m * Cn.y - hD.x), ia * (m * Cn.x - hD.y)};
+    const double ke = (double)n * (n + 1) * ia * ia;
+    C2 nphi = {-dCD.x, -dCD.y};
+    C2 nzeta = {-dAB.x, -dAB.y};
+    C2 ndelta = {dBmA.x + ke * En.x, dBmA.y + ke * En.y};
+    if (m == 0) { nphi.y = 0; nzeta.y = 0; ndelta.y = 0; }
+    st2(F + 2 * (off + n - m), nphi);
+    st2(F + 2 * (K + off + n - m), nzeta);
+    st2(F + 2 * (2 * K + off + n - m), ndelta);
+  }
+}
+
+// -------------------------------------------------------------- implicit
+__device__ __forceinline__ void solve_mode(double lam, double beta, Phys ph, C2 bp, C2 bz, C2 bd,
+                                           C2& xp, C2& xz, C2& xd) {
+  const double d = 1.0 - beta * ph.nu * lam;
+  const double det = d * d - beta * beta * ph.phibar * lam;
+  const double id = 1.0 / d, idet = 1.0 / det;
+  xz = {bz.x * id, bz.y * id};
+  xp = {(d * bp.x - beta * ph.phibar * bd.x) * idet, (d * bp.y - beta * ph.phibar * bd.y) * idet};
+  xd = {(d * bd.x - beta * lam * bp.x) * idet, (d * bd.y - beta * lam * bp.y) * idet};
+}
+
+__global__ void k_implicit_solve(const double* __restrict__ bv, double* __restrict__ x, int T,
+                                 int batch, double beta, Phys ph) {
+  const int K = (T + 1) * (T + 2) / 2;
+  const long long tot = (long long)batch * K;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / K), k = (int)(idx - (long long)b * K);
+    int m, n;
+    slot_mn(T, k, m, n);
+    const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
+    const double* B = bv + (size_t)b * 3 * K * 2;
+    C2 xp, xz, xd;
+    solve_mode(lam, beta, ph, ld2(B + 2 * k), ld2(B + 2 * (K + k)), ld2(B + 2 * (2 * K + k)), xp,
+               xz, xd);
+    double* X = x + (size_t)b * 3 * K * 2;
+    st2(X + 2 * k, xp);
+    st2(X + 2 * (K + k), xz);
+    st2(X + 2 * (2 * K + k), xd);
+  }
+}
+
+// -------------------------------------------------------------- SDC sweep
+struct SdcMat {
+  double Q[81], QE[81], QI[81];
+  int nn;
+};
+
+// S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j) - dt sum_{j=1}^{i-1} qE_ij F_E^j
+//       - dt sum_{j=1}^{i} qI_ij F_I^j + tau_i        (old F, i = 1..M)
+// i.e. every term of the node-i update that uses only the previous iterate.
+template <int NN>
+__global__ void k_sweep_pre(const double* __restrict__ th, const double* __restrict__ fe,
+                            const double* __restrict__ fi, const double* __restrict__ tau,
+                            double* __restrict__ S, int K, int batch, double dt, SdcMat sm) {
+  constexpr int nn = NN, M = NN - 1;
+  const long long tot = (long long)batch * 3 * K;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / (3 * K));
+    const int vk = (int)(idx - (long long)b * 3 * K);
+    const size_t base = (size_t)b * nn * 3 * K;
+    C2 E[NN], I[NN];
+#pragma unroll
+    for (int j = 0; j < nn; ++j) {
+      E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
+      I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
+    }
+    const C2 t0 = ld2(th + 2 * (base + vk));
+#pragma unroll
+    for (int i = 1; i <= M; ++i) {
+      double sx = 0, sy = 0;
+#pragma unroll
+      for (int j = 0; j < nn; ++j) {
+        double c = sm.Q[i * nn + j];
+        sx += c * (E[j].x + I[j].x);
+        sy += c * (E[j].y + I[j].y);
+      }
+#pragma unroll
+      for (int j = 1; j < i; ++j) {
+        sx -= sm.QE[i * nn + j] * E[j].x;
+        sy -= sm.QE[i * nn + j] * E[j].y;
+      }
+#pragma unroll
+      for (int j = 1; j <= i; ++j) {
+        sx -= sm.QI[i * nn + j] * I[j].x;
+        sy -= sm.QI[i * nn + j] * I[j].y;
+      }
+      C2 r = {t0.x + dt * sx, t0.y + dt * sy};
+      if (tau) {
+        const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
+        r.x += tv.x;
+        r.y += tv.y;
+      }
+      st2(S + 2 * (((size_t)b * M + (i - 1)) * 3 * K + vk), r);
+    }
+  }
+}
+
+// node i: b = S_i + dt sum_{j=1}^{i-1} (qE_ij F_E^j + qI_ij F_I^j) (new F), then the
+// implicit solve with beta = dt qI_ii, Theta^i and F_I^i = L Theta^i.
+__global__ void k_sweep_node(double* __restrict__ th, const double* __restrict__ fe,
+                             double* __restrict__ fi, const double* __restrict__ S, int T,
+                             int batch, int node, double dt, SdcMat sm, Phys ph) {
+  const int K = (T + 1) * (T + 2) / 2, nn = sm.nn, M = nn - 1;
+  const long long tot = (long long)batch * K;
+  const double beta = dt * sm.QI[node * nn + node];
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / K), k = (int)(idx - (long long)b * K);
+    int m, n;
+    slot_mn(T, k, m, n);
+    const size_t base = (size_t)b * nn * 3 * K;
+    C2 rhs[3];
+    for (int v = 0; v < 3; ++v) {
+      C2 r = ld2(S + 2 * (((size_t)b * M + (node - 1)) * 3 * K + (size_t)v * K + k));
+      for (int j = 1; j < node; ++j) {
+        const size_t o = base + (size_t)j * 3 * K + (size_t)v * K + k;
+        const C2 e = ld2(fe + 2 * o), f = ld2(fi + 2 * o);
+        const double ce = dt * sm.QE[node * nn + j], ci = dt * sm.QI[node * nn + j];
+        r.x += ce * e.x + ci * f.x;
+        r.y += ce * e.y + ci * f.y;
+      }
+      rhs[v] = r;
+    }
+    const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
+    C2 xp, xz, xd;
+    solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], xp, xz, xd);
+    const size_t o = base + (size_t)node * 3 * K + k;
+    st2(th + 2 * o, xp);
+    st2(th + 2 * (o + K), xz);
+    st2(th + 2 * (o + 2 * K), xd);
+    st2(fi + 2 * o, {-ph.phibar * xd.x + ph.nu * lam * xp.x, -ph.phibar * xd.y + ph.nu * lam * xp.y});
+    st2(fi + 2 * (o + K), {ph.nu * lam * xz.x, ph.nu * lam * xz.y});
+    st2(fi + 2 * (o + 2 * K), {-lam * xp.x + ph.nu * lam * xd.x, -lam * xp.y + ph.nu * lam * xd.y});
+  }
+}
+
+// -------------------------------------------------------------- residual
+__device__ __forceinline__ double nanmax(double r, double a) {
+  return (isnan(a) || a > r) ? a : r;
+}
+
+// partial maxima per (batch, variable, block); |r| with
+// r^i = Theta^0 + dt (Q F)_i + tau_i - Theta^i, i = 1..M
+template <int NN>
+__global__ __launch_bounds__(256) void k_residual_part(const double* __restrict__ th,
+                                                      const double* __restrict__ fe,
+                                                      const double* __restrict__ fi,
+                                                      const double* __restrict__ tau,
+                                                      double* __restrict__ part, int K,
+                                                      double dt, SdcMat sm) {
+  constexpr int nn = NN;
+  const int b = blockIdx.z, v = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double r = 0.0;
+  if (k < K) {
+    const size_t base = (size_t)b * nn * 3 * K + (size_t)v * K + k;
+    C2 F[NN];
+#pragma unroll
+    for (int j = 0; j < nn; ++j) {
+      const C2 e = ld2(fe + 2 * (base + (size_t)j * 3 * K));
+      const C2 f = ld2(fi + 2 * (base + (size_t)j * 3 * K));
+      F[j] = {e.x + f.x, e.y + f.y};
+    }
+    const C2 t0 = ld2(th + 2 * base);
+#pragma unroll
+    for (int i = 1; i < nn; ++i) {
+      double sx = 0, sy = 0;
+#pragma unroll
+      for (int j = 0; j < nn; ++j) {
+        sx += sm.Q[i * nn + j] * F[j].x;
+        sy += sm.Q[i * nn + j] * F[j].y;
+      }
+      const C2 ti = ld2(th + 2 * (base + (size_t)i * 3 * K));
+      double rx = t0.x + dt * sx - ti.x, ry = t0.y + dt * sy - ti.y;
+      if (tau) {
+        const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K));
+        rx += tv.x;
+        ry += tv.y;
+      }
+      r = nanmax(r, sqrt(rx * rx + ry * ry));
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = nanmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[((size_t)b * 3 + v) * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_residual_final(const double* __restrict__ part, double* __restrict__ out,
+                                 int nblk, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double r = 0.0;
+  for (int q = 0; q < nblk; ++q) r = nanmax(r, part[(size_t)i * nblk + q]);
+  out[i] = r;
+}
+
+__global__ void k_count_nonfinite(const double* __restrict__ v, int n, int* __restrict__ flag) {
+  int bad = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (!isfinite(v[i])) bad = 1;
+  if (bad) flag[0] = 1;
+}
+
+// -------------------------------------------------------------- copies
+// node 0 -> nodes 1..M of a [batch][nn][3K] complex array
+__global__ void k_spread(double* __restrict__ a, int nn, long long n3k, int batch) {
+  const long long tot = (long long)batch * (nn - 1) * n3k;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long b = idx / ((nn - 1) * n3k);
+    const long long r = idx - b * (nn - 1) * n3k;
+    const long long i = 1 + r / n3k, e = r - (i - 1) * n3k;
+    const size_t base = (size_t)b * nn * n3k;
+    st2(a + 2 * (base + i * n3k + e), ld2(a + 2 * (base + e)));
+  }
+}
+
+// strided batch copy of n_per complex values
+__global__ void k_copy_state(const double* __restrict__ src, long long sstride,
+                             double* __restrict__ dst, long long dstride, long long n_per,
+                             int batch) {
+  const long long tot = (long long)batch * n_per;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long b = idx / n_per, e = idx - b * n_per;
+    st2(dst + 2 * (b * dstride + e), ld2(src + 2 * (b * sstride + e)));
+  }
+}
+
+// -------------------------------------------------------------- transfers
+struct TMat {
+  double P[81];  // [ndst][nsrc]
+};
+
+// restriction: out_c[b][i][v][kc] = sum_j Pi_cf[i][j] in_f[b][j][v][kf(kc)]
+__global__ void k_restrict(const double* __restrict__ in, double* __restrict__ out, int Tf, int Tc,
+                           int nf, int nc, int batch, TMat pm) {
+  const int Kc = (Tc + 1) * (Tc + 2) / 2, Kf = (Tf + 1) * (Tf + 2) / 2;
+  const long long tot = (long long)batch * nc * 3 * Kc;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long r = idx;
+    const int kc = (int)(r % Kc); r /= Kc;
+    const int v = (int)(r % 3); r /= 3;
+    const int i = (int)(r % nc);
+    const int b = (int)(r / nc);
+    int m, n;
+    slot_mn(Tc, kc, m, n);
+    const int kf = spec_off(Tf, m) + n - m;
+    double sx = 0, sy = 0;
+    for (int j = 0; j < nf; ++j) {
+      const double c = pm.P[i * nf + j];
+      if (c == 0.0) continue;
+      const C2 z = ld2(in + 2 * ((((size_t)b * nf + j) * 3 + v) * Kf + kf));
+      sx += c * z.x;
+      sy += c * z.y;
+    }
+    st2(out + 2 * idx, {sx, sy});
+  }
+}
+
+// interpolation of an increment: inout_f[b][i][v][kf(kc)] += sum_j Pi_fc[i][j] (new - old)[b][j][v][kc]
+__global__ void k_interp_add(const double* __restrict__ nw, const double* __restrict__ old,
+                             double* __restrict__ io, int Tc, int Tf, int nc, int nf, int batch,
+                             TMat pm) {
+  const int Kc = (Tc + 1) * (Tc + 2) / 2, Kf = (Tf + 1) * (Tf + 2) / 2;
+  const long long tot = (long long)batch * nf * 3 * Kc;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long r = idx;
+    const int kc = (int)(r % Kc); r /= Kc;
+    const int v = (int)(r % 3); r /= 3;
+    const int i = (int)(r % nf);
+    const int b = (int)(r / nf);
+    int m, n;
+    slot_mn(Tc, kc, m, n);
+    const int kf = spec_off(Tf, m) + n - m;
+    double sx = 0, sy = 0;
+    for (int j = 0; j < nc; ++j) {
+      const double c = pm.P[i * nc + j];
+      if (c == 0.0) continue;
+      const size_t o = (((size_t)b * nc + j) * 3 + v) * Kc + kc;
+      C2 z = ld2(nw + 2 * o);
+      if (old) {
+        const C2 y = ld2(old + 2 * o);
+        z.x -= y.x;
+        z.y -= y.y;
+      }
+      sx += c * z.x;
+      sy += c * z.y;
+    }
+    double* p = io + 2 * ((((size_t)b * nf + i) * 3 + v) * Kf + kf);
+    C2 t = ld2(p);
+    st2(p, {t.x + sx, t.y + sy});
+  }
+}
+
+// tau_c = dt [ sum_j Pi_cf[i][j] sum_l Qf[j][l] F_f^l (kf)  -  sum_l Qc[i][l] F_c^l (kc) ]
+struct TauMat {
+  double Pcf[81], Qf[81], Qc[81];
+};
+__global__ void k_fas_tau(const double* __restrict__ fef, const double* __restrict__ fif,
+                          const double* __restrict__ fec, const double* __restrict__ fic,
+                          double* __restrict__ tau, int Tf, int Tc, int nf, int nc, int batch,
+                          double dt, TauMat tm) {
+  const int Kc = (Tc + 1) * (Tc + 2) / 2, Kf = (Tf + 1) * (Tf + 2) / 2;
+  const long long tot = (long long)batch * 3 * Kc;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long r = idx;
+    const int kc = (int)(r % Kc); r /= Kc;
+    const int v = (int)(r % 3);
+    const int b = (int)(r / 3);
+    int m, n;
+    slot_mn(Tc, kc, m, n);
+    const int kf = spec_off(Tf, m) + n - m;
+    C2 Ff[9], Fc[9];
+    for (int l = 0; l < nf; ++l) {
+      const size_t o = (((size_t)b * nf + l) * 3 + v) * Kf + kf;
+      const C2 e = ld2(fef + 2 * o), f = ld2(fif + 2 * o);
+      Ff[l] = {e.x + f.x, e.y + f.y};
+    }
+    for (int l = 0; l < nc; ++l) {
+      const size_t o = (((size_t)b * nc + l) * 3 + v) * Kc + kc;
+      const C2 e = ld2(fec + 2 * o), f = ld2(fic + 2 * o);
+      Fc[l] = {e.x + f.x, e.y + f.y};
+    }
+    for (int i = 0; i < nc; ++i) {
+      double fx = 0, fy = 0;
+      for (int j = 0; j < nf; ++j) {
+        const double c = tm.Pcf[i * nf + j];
+        if (c == 0.0) continue;
+        double qx = 0, qy = 0;
+        for (int l = 0; l < nf; ++l) {
+          qx += tm.Qf[j * nf + l] * Ff[l].x;
+          qy += tm.Qf[j * nf + l] * Ff[l].y;
+        }
+        fx += c * qx;
+        fy += c * qy;
+      }
+      double cx = 0, cy = 0;
+      for (int l = 0; l < nc; ++l) {
+        cx += tm.Qc[i * nc + l] * Fc[l].x;
+        cy += tm.Qc[i * nc + l] * Fc[l].y;
+      }
+      st2(tau + 2 * ((((size_t)b * nc + i) * 3 + v) * Kc + kc), {dt * fx - dt * cx, dt * fy - dt * cy});
+    }
+  }
+}
+
+// PFASST step D: new fine initial condition = received fine value with its
+// (m, n <= Tc) modes moved by (coarse initial condition - restriction of it).
+__global__ void k_ic_correct(const double* __restrict__ recv, long long rstride,
+                             const double* __restrict__ icc, long long cstride,
+                             double* __restrict__ out, long long ostride, int Tf, int Tc,
+                             int batch) {
+  const int Kf = (Tf + 1) * (Tf + 2) / 2, Kc = (Tc + 1) * (Tc + 2) / 2;
+  const long long tot = (long long)batch * 3 * Kf;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / (3 * Kf));
+    const int r = (int)(idx - (long long)b * 3 * Kf);
+    const int v = r / Kf, kf = r - v * Kf;
+    int m, n;
+    slot_mn(Tf, kf, m, n);
+    C2 z = ld2(recv + 2 * ((size_t)b * rstride + r));
+    if (m <= Tc && n <= Tc) {
+      const int kc = spec_off(Tc, m) + n - m;
+      const C2 c = ld2(icc + 2 * ((size_t)b * cstride + (size_t)v * Kc + kc));
+      z = {z.x + (c.x - z.x), z.y + (c.y - z.y)};
+    }
+    st2(out + 2 * ((size_t)b * ostride + r), z);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblocks(long long work, int bs) {
+  long long g = (work + bs - 1) / bs;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (unsigned)g;
+}
+static inline Phys phys_of(const pfsh_level* lv) {
+  return Phys{lv->d.radius, lv->d.omega, lv->d.phibar, lv->d.nu};
+}
+static inline SdcMat sdc_of(const pfsh_level* lv) {
+  SdcMat s;
+  for (int i = 0; i < 81; ++i) { s.Q[i] = lv->Q[i]; s.QE[i] = lv->QE[i]; s.QI[i] = lv->QI[i]; }
+  s.nn = lv->nn;
+  return s;
+}
+
+hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long sstride,
+                           double* f_impl, long long fstride, int batch, hipStream_t s) {
+  dim3 grid(lv->L, batch);
+  switch (lv->op) {
+    case OP_F64:
+      hipLaunchKernelGGL(k_prep_rhs<OpF64>, grid, dim3(128), 0, s, state, sstride, f_impl,
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, phys_of(lv));
+      break;
+    case OP_F32:
+      hipLaunchKernelGGL(k_prep_rhs<OpF32>, grid, dim3(128), 0, s, state, sstride, f_impl,
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, phys_of(lv));
+      break;
+    default:
+      hipLaunchKernelGGL(k_prep_rhs<OpBF3>, grid, dim3(128), 0, s, state, sstride, f_impl,
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, phys_of(lv));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_scalar(const pfsh_level* lv, const double* spec, int nfields, hipStream_t s) {
+  dim3 grid(lv->L, nfields);
+  switch (lv->op) {
+    case OP_F64:
+      hipLaunchKernelGGL(k_prep_scalar<OpF64>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
+                         lv->T, lv->CBs);
+      break;
+    case OP_F32:
+      hipLaunchKernelGGL(k_prep_scalar<OpF32>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
+                         lv->T, lv->CBs);
+      break;
+    default:
+      hipLaunchKernelGGL(k_prep_scalar<OpBF3>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
+                         lv->T, lv->CBs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_scalar(const pfsh_level* lv, double* spec, int nfields, hipStream_t s) {
+  const long long work = (long long)nfields * lv->K;
+  if (lv->op == OP_F64)
+    hipLaunchKernelGGL(k_unpack_scalar<double>, dim3(nblocks(work, 256)), dim3(256), 0, s,
+                       (const double*)lv->Y, spec, lv->T, nfields);
+  else
+    hipLaunchKernelGGL(k_unpack_scalar<float>, dim3(nblocks(work, 256)), dim3(256), 0, s,
+                       (const float*)lv->Y, spec, lv->T, nfields);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fstride, int batch,
+                           hipStream_t s) {
+  dim3 grid(lv->L, batch);
+  if (lv->op == OP_F64)
+    hipLaunchKernelGGL(k_assemble<double>, grid, dim3(128), 0, s, (const double*)lv->Y, f_expl,
+                       fstride, lv->T, lv->d.radius);
+  else
+    hipLaunchKernelGGL(k_assemble<float>, grid, dim3(128), 0, s, (const float*)lv->Y, f_expl,
+                       fstride, lv->T, lv->d.radius);
+  return hipGetLastError();
+}
+
+hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double* b, double* x,
+                                 int batch, hipStream_t s) {
+  const long long work = (long long)batch * lv->K;
+  hipLaunchKernelGGL(k_implicit_solve, dim3(nblocks(work, 256)), dim3(256), 0, s, b, x, lv->T,
+                     batch, beta, phys_of(lv));
+  return hipGetLastError();
+}
+
+#define PFSH_NN_SWITCH(nn, CALL) \
+  switch (nn) {                  \
+    case 2: CALL(2); break;      \
+    case 3: CALL(3); break;      \
+    case 4: CALL(4); break;      \
+    case 5: CALL(5); break;      \
+    case 6: CALL(6); break;      \
+    case 7: CALL(7); break;      \
+    case 8: CALL(8); break;      \
+    default: CALL(9); break;     \
+  }
+
+hipError_t launch_sweep_pre(const pfsh_level* lv, double dt, const double* theta, const double* fe,
+                            const double* fi, const double* tau, int batch, hipStream_t s) {
+  const long long work = (long long)batch * 3 * lv->K;
+  const SdcMat sm = sdc_of(lv);
+#define PFSH_PRE(NN)                                                                           \
+  hipLaunchKernelGGL(k_sweep_pre<NN>, dim3(nblocks(work, 256)), dim3(256), 0, s, theta, fe, fi, \
+                     tau, lv->S, lv->K, batch, dt, sm)
+  PFSH_NN_SWITCH(lv->nn, PFSH_PRE)
+#undef PFSH_PRE
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_node(const pfsh_level* lv, int node, double dt, double* theta,
+                             const double* fe, double* fi, int batch, hipStream_t s) {
+  const long long work = (long long)batch * lv->K;
+  hipLaunchKernelGGL(k_sweep_node, dim3(nblocks(work, 256)), dim3(256), 0, s, theta, fe, fi,
+                     lv->S, lv->T, batch, node, dt, sdc_of(lv), phys_of(lv));
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
+                           const double* fi, const double* tau, double* out, int batch,
+                           hipStream_t s) {
+  const int nblk = (lv->K + 255) / 256;
+  const SdcMat sm = sdc_of(lv);
+#define PFSH_RES(NN)                                                                          \
+  hipLaunchKernelGGL(k_residual_part<NN>, dim3(nblk, 3, batch), dim3(256), 0, s, theta, fe, fi, \
+                     tau, lv->red, lv->K, dt, sm)
+  PFSH_NN_SWITCH(lv->nn, PFSH_RES)
+#undef PFSH_RES
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_residual_final, dim3((batch * 3 + 127) / 128), dim3(128), 0, s, lv->red,
+                     out, nblk, batch * 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_spread(const pfsh_level* lv, double* a, int batch, hipStream_t s) {
+  const long long n3k = 3LL * lv->K;
+  const long long work = (long long)batch * (lv->nn - 1) * n3k;
+  hipLaunchKernelGGL(k_spread, dim3(nblocks(work, 256)), dim3(256), 0, s, a, lv->nn, n3k, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const double* src, long long sstride, double* dst, long long dstride,
+                             long long n_per, int batch, hipStream_t s) {
+  const long long work = (long long)batch * n_per;
+  hipLaunchKernelGGL(k_copy_state, dim3(nblocks(work, 256)), dim3(256), 0, s, src, sstride, dst,
+                     dstride, n_per, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const pfsh_level* f, const pfsh_level* c, const double* in_f,
+                           double* out_c, int batch, hipStream_t s) {
+  TMat pm;
+  lagrange_matrix(f->nn, f->nodes, c->nn, c->nodes, pm.P);
+  const long long work = (long long)batch * c->nn * 3 * c->K;
+  hipLaunchKernelGGL(k_restrict, dim3(nblocks(work, 256)), dim3(256), 0, s, in_f, out_c, f->T,
+                     c->T, f->nn, c->nn, batch, pm);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_add(const pfsh_level* c, const pfsh_level* f, const double* new_c,
+                             const double* old_c, double* inout_f, int batch, hipStream_t s) {
+  TMat pm;
+  lagrange_matrix(c->nn, c->nodes, f->nn, f->nodes, pm.P);
+  const long long work = (long long)batch * f->nn * 3 * c->K;
+  hipLaunchKernelGGL(k_interp_add, dim3(nblocks(work, 256)), dim3(256), 0, s, new_c, old_c,
+                     inout_f, c->T, f->T, c->nn, f->nn, batch, pm);
+  return hipGetLastError();
+}
+
+hipError_t launch_fas_tau(const pfsh_level* f, const pfsh_level* c, double dt, const double* fe_f,
+                          const double* fi_f, const double* fe_c, const double* fi_c, double* tau,
+                          int batch, hipStream_t s) {
+  TauMat tm;
+  lagrange_matrix(f->nn, f->nodes, c->nn, c->nodes, tm.Pcf);
+  for (int i = 0; i < 81; ++i) { tm.Qf[i] = 0; tm.Qc[i] = 0; }
+  for (int i = 0; i < f->nn * f->nn; ++i) tm.Qf[i] = f->Q[i];
+  for (int i = 0; i < c->nn * c->nn; ++i) tm.Qc[i] = c->Q[i];
+  const long long work = (long long)batch * 3 * c->K;
+  hipLaunchKernelGGL(k_fas_tau, dim3(nblocks(work, 256)), dim3(256), 0, s, fe_f, fi_f, fe_c, fi_c,
+                     tau, f->T, c->T, f->nn, c->nn, batch, dt, tm);
+  return hipGetLastError();
+}
+
+hipError_t launch_ic_correct(const pfsh_level* f, const pfsh_level* c, const double* recv_f,
+                             long long recv_stride, const double* ic_c, long long ic_stride,
+                             double* out_f, long long out_stride, int batch, hipStream_t s) {
+  const long long work = (long long)batch * 3 * f->K;
+  hipLaunchKernelGGL(k_ic_correct, dim3(nblocks(work, 256)), dim3(256), 0, s, recv_f, recv_stride,
+                     ic_c, ic_stride, out_f, out_stride, f->T, c->T, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const double* v, int n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(nblocks(n, 256)), dim3(256), 0, s, v, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace pfsh

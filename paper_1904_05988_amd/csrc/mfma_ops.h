@@ -1,0 +1,115 @@
+// MFMA operand types of the three transform precisions (gfx950).
+//
+//   OpF64   v_mfma_f64_16x16x4_f64            FP64 operands, FP64 accumulate
+//   OpF32   v_mfma_f32_16x16x4_f32            FP32 operands, FP32 accumulate
+//   OpBF3   v_mfma_f32_16x16x32_bf16 (x3)     x = hi + lo (bf16 each), products
+//                                             hi*hi + hi*lo + lo*hi, FP32 accumulate
+// Operand blocks: lane l holds A[l % 16][k] and B[k][l % 16] with k = l / 16
+// (16x16x4) or k = 8 (l / 16) + e, e = 0..7 (16x16x32).  A 16x16 output block
+// holds column l % 16 in lane l; the rows differ: FP32 and BF16 accumulate rows
+// 4 (l / 16) + v, FP64 rows (l / 16) + 4 v, v = 0..3 (checked on gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pfsh_internal.h"
+
+namespace pfsh {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+struct Bf16Pair {
+  bf8_t hi, lo;
+};
+
+__device__ __forceinline__ unsigned short bf16_bits_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+struct OpF64 {
+  typedef double R;       // transform real type
+  typedef double Acc;     // accumulator scalar
+  typedef double A;       // per-lane operand
+  typedef d4_t C;
+  static constexpr int KIND = OP_F64;
+  static constexpr int KB = 4;
+  __device__ static __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+  __device__ static __forceinline__ A load(const void* base, long long blk, int lane) {
+    return reinterpret_cast<const double*>(base)[blk * 64 + lane];
+  }
+  __device__ static __forceinline__ A zero() { return 0.0; }
+  __device__ static __forceinline__ C mma(A a, A b, C c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ void store(void* base, long long blk, int lane, int, R v) {
+    reinterpret_cast<double*>(base)[blk * 64 + lane] = v;
+  }
+};
+
+struct OpF32 {
+  typedef float R;
+  typedef float Acc;
+  typedef float A;
+  typedef f4_t C;
+  static constexpr int KIND = OP_F32;
+  static constexpr int KB = 4;
+  __device__ static __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  __device__ static __forceinline__ A load(const void* base, long long blk, int lane) {
+    return reinterpret_cast<const float*>(base)[blk * 64 + lane];
+  }
+  __device__ static __forceinline__ A zero() { return 0.0f; }
+  __device__ static __forceinline__ C mma(A a, A b, C c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ void store(void* base, long long blk, int lane, int, R v) {
+    reinterpret_cast<float*>(base)[blk * 64 + lane] = v;
+  }
+};
+
+struct OpBF3 {
+  typedef float R;
+  typedef float Acc;
+  typedef Bf16Pair A;
+  typedef f4_t C;
+  static constexpr int KIND = OP_BF16X3;
+  static constexpr int KB = 32;
+  __device__ static __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  __device__ static __forceinline__ A load(const void* base, long long blk, int lane) {
+    const bf8_t* p = reinterpret_cast<const bf8_t*>(base) + (blk * 64 + lane) * 2;
+    A a;
+    a.hi = p[0];
+    a.lo = p[1];
+    return a;
+  }
+  __device__ static __forceinline__ A zero() {
+    A a;
+    for (int i = 0; i < 8; ++i) {
+      a.hi[i] = (__bf16)0.0f;
+      a.lo[i] = (__bf16)0.0f;
+    }
+    return a;
+  }
+  __device__ static __forceinline__ C mma(const A& a, const A& b, C c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
+    return c;
+  }
+  // element e of lane `lane`: hi at [lane*16 + e], lo at [lane*16 + 8 + e]
+  __device__ static __forceinline__ void store(void* base, long long blk, int lane, int e, R v) {
+    unsigned short* h = reinterpret_cast<unsigned short*>(base) + (blk * 64 + lane) * 16;
+    unsigned short hi = bf16_bits_rne(v);
+    unsigned short lo = bf16_bits_rne(v - bf16_bits_to_float(hi));
+    h[e] = hi;
+    h[8 + e] = lo;
+  }
+};
+
+}  // namespace pfsh

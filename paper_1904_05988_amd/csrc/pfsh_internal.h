@@ -1,0 +1,138 @@
+// Internal definitions of libpfsh: level object, packed-operand layouts and
+// kernel launchers shared by the host API and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "pfsh.h"
+
+namespace pfsh {
+
+// ---------------------------------------------------------------- layouts
+// Spectral m-major slot of (m, n), n = m..T.
+__host__ __device__ inline int spec_off(int T, int m) { return m * (T + 1) - m * (m - 1) / 2; }
+// Extended m-major slot of (m, n), n = m..T+1 (the transform stages work to
+// degree T+1 so that (1-mu^2) dP/dmu folds into P contractions).
+__host__ __device__ inline int ext_off(int T, int m) { return m * (T + 2) - m * (m - 1) / 2; }
+// Number of degrees n = m+p, m+p+2, ... <= T+1 of parity p for order m.
+__host__ __device__ inline int npar(int T, int m, int p) {
+  return (m + p <= T + 1) ? ((T + 1 - m - p) / 2 + 1) : 0;
+}
+
+// MFMA operand blocks.  FP64/FP32 use 16x16x4 MFMA: a block is 16 (row or
+// column) x 4 (k) elements and lane l holds element (l % 16, l / 16).  BF16x3
+// uses 16x16x32 MFMA: a block is 16 x 32 and lane l holds elements
+// (l % 16, 8 (l / 16) + e), e = 0..7, stored as 8 hi then 8 lo bf16 values.
+enum OpKind { OP_F64 = 0, OP_F32 = 1, OP_BF16X3 = 2 };
+__host__ __device__ inline int op_kb(int op) { return op == OP_BF16X3 ? 32 : 4; }
+// bytes of one 64-lane block
+__host__ __device__ inline int op_block_bytes(int op) {
+  return op == OP_F64 ? 64 * 8 : (op == OP_F32 ? 64 * 4 : 64 * 16 * 2);
+}
+// lane and element of (r, k) inside a block (k < KB)
+__host__ __device__ inline int op_lane(int op, int r, int k) {
+  return op == OP_BF16X3 ? ((k >> 3) << 4) + r : (k << 4) + r;
+}
+__host__ __device__ inline int op_elem(int op, int k) { return op == OP_BF16X3 ? (k & 7) : 0; }
+
+// Per-(m, p) bookkeeping of the packed tables and operands (index mp = 2m+p).
+struct MPInfo {
+  int m, p, np;       // order, parity, number of degrees
+  int kbS;            // synthesis: k-blocks (ceil(np / KB))
+  int rbA;            // analysis: row blocks (ceil(np / 16))
+  long long tabS;     // synthesis table: first block
+  long long tabA;     // analysis table: first block
+  long long xS;       // synthesis data operand: first block
+};
+
+struct WorkItem {      // one workgroup tile of a Legendre contraction
+  int mp;              // (m, p) index
+  int tile;            // row tile (64 rows)
+};
+
+}  // namespace pfsh
+
+struct pfsh_level {
+  pfsh_level_desc d;
+  int device;
+  int op;                  // pfsh::OpKind
+  int T, L, K, Kx, J, Jp, nlat, nlon, nn, M;
+  int KB, RB, kb2;         // k-block, synthesis row blocks (Jp/16), analysis k-blocks (Jp/KB)
+  int CBs, CBa;            // column blocks of the synthesis / analysis data operands
+  std::vector<pfsh::MPInfo> mp;
+  std::vector<double> mu_h, w_h;          // full grid, north to south
+  double nodes[9], Q[81], QE[81], QI[81];
+  // device tables
+  void* tabS = nullptr;    // packed synthesis table (A operand, rows = rings)
+  void* tabA = nullptr;    // packed analysis table (A operand, rows = degrees)
+  pfsh::MPInfo* mp_d = nullptr;
+  pfsh::WorkItem* itemsS = nullptr;  int nitemsS = 0;
+  pfsh::WorkItem* itemsA = nullptr;  int nitemsA = 0;
+  double* mu_d = nullptr;  // [J] northern Gaussian latitudes
+  double* w_d = nullptr;   // [J] weights
+  void* tw_d = nullptr;    // [nlon] e^{2 pi i t/nlon} in the transform real type
+  double* eps_d = nullptr; // [Kx] eps_n^m of the extended layout
+  // workspace
+  void* X = nullptr;       // synthesis data operand
+  void* F4 = nullptr;      // Fourier coefficients [batch][J][nf][2][L] complex (transform type)
+  void* G = nullptr;       // analysis data operand
+  void* Y = nullptr;       // analysis result [batch*5][Kx] complex (transform accumulate type)
+  double* S = nullptr;     // sweep pre-accumulation [batch][M][3][K] complex
+  double* red = nullptr;   // residual partial maxima
+  size_t red_len = 0;
+  size_t bytes_tables = 0, bytes_work = 0;
+};
+
+namespace pfsh {
+
+// ------------------------------------------------------------- host tables
+void gauss_legendre(int nlat, std::vector<double>& mu, std::vector<double>& w);
+void sdc_matrices(int nn, double* nodes, double* Q, double* QE, double* QI);
+void lagrange_matrix(int nsrc, const double* src, int ndst, const double* dst, double* out);
+// Build packed tables for a level (host), returns bytes.
+void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<unsigned char>& tabA,
+                  std::vector<double>& eps_ext);
+
+// ------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error.
+hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s);
+hipError_t launch_leg_anal(const pfsh_level* lv, int ncols, int nf, hipStream_t s);
+hipError_t launch_ring_rhs(const pfsh_level* lv, int batch, hipStream_t s);
+hipError_t launch_ring_synth(const pfsh_level* lv, int nfields, double* grid, hipStream_t s);
+hipError_t launch_ring_anal(const pfsh_level* lv, int nfields, const double* grid, hipStream_t s);
+
+// spectral kernels (FP64)
+hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long state_stride,
+                           double* f_impl, long long fi_stride, int batch, hipStream_t s);
+hipError_t launch_prep_scalar(const pfsh_level* lv, const double* spec, int nfields, hipStream_t s);
+hipError_t launch_unpack_scalar(const pfsh_level* lv, double* spec, int nfields, hipStream_t s);
+hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fe_stride, int batch,
+                           hipStream_t s);
+hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double* b, double* x,
+                                 int batch, hipStream_t s);
+hipError_t launch_sweep_pre(const pfsh_level* lv, double dt, const double* theta, const double* fe,
+                            const double* fi, const double* tau, int batch, hipStream_t s);
+hipError_t launch_sweep_node(const pfsh_level* lv, int node, double dt, double* theta,
+                             const double* fe, double* fi, int batch, hipStream_t s);
+hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
+                           const double* fi, const double* tau, double* out, int batch,
+                           hipStream_t s);
+hipError_t launch_spread(const pfsh_level* lv, double* a, int batch, hipStream_t s);
+hipError_t launch_restrict(const pfsh_level* f, const pfsh_level* c, const double* in_f,
+                           double* out_c, int batch, hipStream_t s);
+hipError_t launch_interp_add(const pfsh_level* c, const pfsh_level* f, const double* new_c,
+                             const double* old_c, double* inout_f, int batch, hipStream_t s);
+hipError_t launch_fas_tau(const pfsh_level* f, const pfsh_level* c, double dt, const double* fe_f,
+                          const double* fi_f, const double* fe_c, const double* fi_c, double* tau,
+                          int batch, hipStream_t s);
+hipError_t launch_ic_correct(const pfsh_level* f, const pfsh_level* c, const double* recv_f,
+                             long long recv_stride, const double* ic_c, long long ic_stride,
+                             double* out_f, long long out_stride, int batch, hipStream_t s);
+hipError_t launch_copy_state(const double* src, long long src_stride, double* dst,
+                             long long dst_stride, long long n_per, int batch, hipStream_t s);
+hipError_t launch_count_nonfinite(const double* v, int n, int* flag, hipStream_t s);
+
+}  // namespace pfsh
