@@ -1,0 +1,317 @@
+"""Throughput of the PFASST-SH hot path on one MI355X.
+
+Workload: two-level PFASST on one GPU, fine T255 (384 x 768 Gaussian grid, 5
+Gauss-Lobatto nodes) / coarse T127 (192 x 384, 3 nodes), 16 time slices of
+dt = 60 s advanced as one batch, seeded synthetic initial state (n^-2 spectra,
+balanced 20 m/s solid body).  One timed step is one PFASST block: the
+predictor and N_PF = 8 iterations of Algorithm 1 (the batched fine SDC sweep
+of all 16 slices, restriction, coarse F and FAS correction, the serial coarse
+chain, interpolation of the increments, new initial conditions; the last
+iteration stops after its fine sweep), then the fine collocation residual.
+"sweeps/s" counts batched fine sweeps (all 16 slices) per second.
+
+The headline block runs the transform stages in mixed precision (FP32 by
+default) and its last two iterations with FP64 fine levels; the same block in
+plain FP64 is timed next to it, and the final states of the two are compared.
+Iterations are replayed from captured HIP graphs.  The dominant kernel's
+roofline fraction is measured with HIP events around its launches in a second
+pass over the same blocks with direct launches; the oracle is timed on the
+host cores on a bounded sample.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU (time slices are the batch axis).
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "SDC sweeps/s at T255 x16 slices: mixed vs FP64 at <=1e-6 rel err; SHT TFLOP/s"
+FINE = (255, 384, 768, 5)
+COARSE = (127, 192, 384, 3)
+N_TS = 16
+DT = 60.0
+SEED = 3
+PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}   # dense MFMA TFLOP/s
+HBM_PEAK = 8000.0  # GB/s
+
+
+def npar(T, m, p):
+    return (T + 1 - m - p) // 2 + 1 if m + p <= T + 1 else 0
+
+
+def legendre_flops(T, nlat, ncols):
+    """Useful multiply-adds x 2 of one Legendre contraction (all m, both
+    parities, northern rings, degrees to T+1) over `ncols` real columns."""
+    J = nlat // 2
+    deg = sum(npar(T, m, p) for m in range(T + 1) for p in (0, 1))
+    return 2.0 * deg * J * ncols
+
+
+def ring_flops(nlat, nlon, batch, nsig=9):
+    """5 N log2 N per complex FFT of length nlon, 9 per ring pair (4 inverse,
+    5 forward)."""
+    return 5.0 * nlon * math.log2(nlon) * nsig * (nlat // 2) * batch
+
+
+def rhs_sht_flops(T, nlat, nlon, batch):
+    return (legendre_flops(T, nlat, 8 * batch) + legendre_flops(T, nlat, 10 * batch)
+            + ring_flops(nlat, nlon, batch))
+
+
+def block_sht_flops(fine, coarse, n_ts, n_pf):
+    """Algorithmic SHT flops of one PFASST block (predictor + n_pf iterations,
+    the last stopping after the fine sweep), counted per RHS evaluation."""
+    Tf, nlf, nof, nnf = fine
+    Tc, nlc, noc, nnc = coarse
+    fr = lambda b: rhs_sht_flops(Tf, nlf, nof, b)
+    cr = lambda b: rhs_sht_flops(Tc, nlc, noc, b)
+    f = cr(n_ts)                                                # predictor: coarse F at the IC
+    for j in range(n_ts):                                       # wavefront stages
+        if j >= 1:
+            f += cr(n_ts - j)
+        f += (nnc - 1) * cr(n_ts - j)
+    f += nnf * fr(n_ts)                                         # fine F at all nodes
+    for k in range(n_pf):
+        f += (nnf - 1) * fr(n_ts)                               # A
+        if k == n_pf - 1:
+            break
+        f += nnc * cr(n_ts)                                     # B
+        f += (n_ts - 1) * cr(1) + n_ts * (nnc - 1) * cr(1)      # C
+        f += fr(n_ts)                                           # D
+    return f
+
+
+def ring_bytes(T, nlat, rsz, batch):
+    """Algorithmic HBM bytes of one fused ring launch: Fourier coefficients of
+    4 fields in (parity form, complex) and of 5 fields out."""
+    L, J = T + 1, nlat // 2
+    return (4 + 5) * 2 * L * J * batch * 2 * rsz
+
+
+def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
+    """K timed PFASST blocks: iterations 1..N_PF-n64 with the `mixed` transform
+    precision, the last n64 with FP64 fine levels (coarse stays `mixed`)."""
+    dev = torch.device("cuda", 0)
+    Tf, nlf, nof, nnf = FINE
+    Tc, nlc, noc, nnc = COARSE
+    B = N_TS
+    gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=mixed)
+    gcm = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B, precision=mixed)
+    gf64 = gfm if mixed == "fp64" else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
+    pf = pfsh.Pfasst(gfm, gcm, N_TS)
+    th0 = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to(dev)
+    thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
+    res = torch.empty((B, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    pf.set_graphs(not profile)
+
+    def block():
+        pf.set_levels(gfm, gcm)
+        pf.predict(DT, th0, thf, fef, fif)
+        for k in range(args.n_pf):
+            if k == args.n_pf - n64:
+                pf.set_levels(gf64, gcm)
+            pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
+        gf64.residual(DT, thf, fef, fif, out=res)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            block()
+        torch.cuda.synchronize()
+        if profile:
+            gfm.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            block()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = None
+        if profile:
+            gfm.profile(False)
+            prof = {k: gfm.profile_read(k) for k in gfm.KERNELS}
+        # sweep-only time of the batched fine sweep
+        s0 = time.perf_counter()
+        for _ in range(10):
+            gfm.sdc_sweep(DT, thf, fef, fif)
+        torch.cuda.synchronize()
+        sweep_ms = (time.perf_counter() - s0) * 1e3 / 10
+    final = None
+    pf.set_graphs(False)
+    pf.close()
+    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, sweep_ms=sweep_ms, resid=res.cpu().numpy(),
+                final=final)
+
+
+def run_state(args, mixed, n64, torch, pfsh, inputs):
+    """One block from the seeded state; returns the fine last-node values."""
+    dev = torch.device("cuda", 0)
+    Tf, nlf, nof, nnf = FINE
+    Tc, nlc, noc, nnc = COARSE
+    B = N_TS
+    gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=mixed)
+    gcm = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B, precision=mixed)
+    gf64 = gfm if mixed == "fp64" else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
+    pf = pfsh.Pfasst(gfm, gcm, N_TS)
+    th0 = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to(dev)
+    thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
+    pf.predict(DT, th0, thf, fef, fif)
+    for k in range(args.n_pf):
+        if k == args.n_pf - n64:
+            pf.set_levels(gf64, gcm)
+        pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
+    out = thf[:, -1].cpu().numpy()
+    pf.close()
+    return out
+
+
+def rel_err(a, b):
+    out = []
+    for v in range(3):
+        ref = b[:, v].copy()
+        if v == 0:
+            ref[:, 0] = 0.0
+        out.append(float(np.abs(a[:, v] - b[:, v]).max() / np.abs(ref).max()))
+    return out
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """The oracle as it stands, on the host: each slice's share of one PFASST
+    iteration (fine sweep, restriction, coarse F and tau, coarse F at node 0
+    and coarse sweep, interpolation of the three increments, fine F at node 0),
+    for as many slices as fit the budget; scaled to iterations/s of 16 slices."""
+    from oracle import sdc, swe, transfer
+    from paper_1904_05988_amd import inputs
+    Tf, nlf, nof, nnf = FINE
+    Tc, nlc, noc, nnc = COARSE
+    lf, lc = swe.Level(Tf, nlf, nof), swe.Level(Tc, nlc, noc)
+    sf, sc = sdc.SDC(nnf), sdc.SDC(nnc)
+    x0 = inputs.seeded_state(Tf, SEED)
+    th, fe, fi = sdc.spread(lf, x0, nnf)
+    done, wall0, cpu0 = 0, time.perf_counter(), time.process_time()
+    while True:
+        t, e, i = sdc.sweep(lf, sf, DT, th, fe, fi)
+        tc = transfer.restrict(sf, sc, Tf, Tc, t)
+        ec = np.array([swe.explicit_rhs(lc, x) for x in tc])
+        ic = np.array([swe.implicit_rhs(lc, x) for x in tc])
+        tau = transfer.fas_tau(sf, sc, Tf, Tc, DT, e, i, ec, ic)
+        ec[0], ic[0] = swe.rhs(lc, tc[0])
+        tc2, ec2, ic2 = sdc.sweep(lc, sc, DT, tc, ec, ic, tau)
+        t = t + transfer.interpolate(sc, sf, Tc, Tf, tc2 - tc)
+        e = e + transfer.interpolate(sc, sf, Tc, Tf, ec2 - ec)
+        i = i + transfer.interpolate(sc, sf, Tc, Tf, ic2 - ic)
+        e[0], i[0] = swe.rhs(lf, t[0])
+        done += 1
+        if time.perf_counter() - wall0 > seconds_budget or done >= N_TS:
+            break
+    wall = time.perf_counter() - wall0
+    cpu = time.process_time() - cpu0
+    per_slice = wall / done
+    return {"value": 1.0 / (per_slice * N_TS), "unit": "sweeps/s", "kind": "oracle",
+            "cores": max(1, int(round(cpu / wall))),
+            "sample": f"{done} of {N_TS} slices' share of one PFASST iteration at T255/T127 "
+                      f"({wall:.1f} s), scaled to all {N_TS} slices"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed PFASST blocks")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--n64", type=int, default=2,
+                    help="final PFASST iterations with FP64 fine levels in the mixed block")
+    ap.add_argument("--n-pf", type=int, default=8, help="PFASST iterations per block")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (time slices are its batch axis); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1904_05988_amd import inputs, pfsh
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}))
+        return
+    pfsh.lib()   # fails loudly if the HIP library is not built
+
+    r64 = run_gpu(args, "fp64", 0, torch, pfsh, inputs)
+    rmx = run_gpu(args, args.mixed, args.n64, torch, pfsh, inputs)
+    # the same timed blocks again with direct launches and HIP events per kernel
+    rpr = run_gpu(args, args.mixed, args.n64, torch, pfsh, inputs, profile=True)
+    x64 = run_state(args, "fp64", 0, torch, pfsh, inputs)
+    xmx = run_state(args, args.mixed, args.n64, torch, pfsh, inputs)
+    xpure = run_state(args, args.mixed, 0, torch, pfsh, inputs)
+    err = rel_err(xmx, x64)
+    err_pure = rel_err(xpure, x64)
+
+    # dominant kernel of the mixed-precision fine level and its roofline
+    prof = rpr["prof"]
+    dom = max(prof, key=lambda k: prof[k][1])
+    Tf, nlf, nof, nnf = FINE
+    n, tot = prof[dom]
+    avg_s = tot / max(n, 1) * 1e-3
+    rsz = 8 if args.mixed == "fp64" else 4
+    if dom in ("leg_synth", "leg_anal"):
+        ncols = (8 if dom == "leg_synth" else 10) * N_TS
+        work = legendre_flops(Tf, nlf, ncols)
+        roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAKS[args.mixed],
+                "unit": "TFLOP/s"}
+    else:
+        work = ring_bytes(Tf, nlf, rsz, N_TS)
+        roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launches"] = n
+    roof["avg_us"] = avg_s * 1e6
+
+    sht = block_sht_flops(FINE, COARSE, N_TS, args.n_pf)
+    value = args.n_pf * 1e3 / rmx["ms"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "sweeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": rmx["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"{args.mixed}+f64", "data": "synthetic",
+        "config": {"workload": "pfasst_t255_t127_16slices", "fine": "T255 384x768 5 Lobatto nodes",
+                   "coarse": "T127 192x384 3 nodes", "slices": N_TS, "dt_s": DT,
+                   "n_pf": args.n_pf, "fp64_final_iterations": args.n64,
+                   "step": "one PFASST block: predictor + n_pf iterations, fine residual",
+                   "seed": SEED, "parallelism": "slices as batch, 1 GPU"},
+        "roofline": roof,
+        "fp64": {"sweeps_per_s": args.n_pf * 1e3 / r64["ms"], "ms_per_step": r64["ms"],
+                 "sweep_only_ms": r64["sweep_ms"],
+                 "sht_tflops": sht / (r64["ms"] * 1e-3) / 1e12},
+        "mixed_rel_err_vs_fp64": err,
+        "mixed_ok": bool(max(err) <= 1e-6),
+        "mixed_without_fp64_iterations_rel_err": err_pure,
+        "sweep_only_ms": rmx["sweep_ms"],
+        "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

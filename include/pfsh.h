@@ -177,6 +177,25 @@ pfsh_status pfsh_fas_tau(const pfsh_level* fine, const pfsh_level* coarse, doubl
                          const void* fe_f, const void* fi_f, const void* fe_c, const void* fi_c,
                          void* tau_c, int batch, void* stream);
 
+/* Kernel timing (diagnostic).  While enabled on a level, every launch of the
+ * listed kernels made through that level is bracketed by HIP events recorded
+ * on the launch stream.  pfsh_profile_read synchronizes on the recorded events
+ * and returns the number of bracketed launches and the sum of their durations
+ * in milliseconds since the last enable.  Enabling clears earlier records.
+ * Not to be enabled while a stream is being captured into a graph. */
+typedef enum {
+  PFSH_K_LEG_SYNTH = 0,   /* Legendre synthesis contraction (MFMA)        */
+  PFSH_K_RING = 1,        /* ring FFTs + grid products                     */
+  PFSH_K_LEG_ANAL = 2,    /* Legendre analysis contraction (MFMA)          */
+  PFSH_K_ASSEMBLE = 3,    /* spectral assembly of F_E                      */
+  PFSH_K_PREP = 4,        /* transform input preparation                   */
+  PFSH_K_SWEEP_NODE = 5,  /* per-node SDC update and implicit solve        */
+  PFSH_K_SWEEP_PRE = 6,   /* per-sweep SDC accumulation of old terms       */
+  PFSH_K_COUNT = 7
+} pfsh_kernel_id;
+pfsh_status pfsh_profile_enable(pfsh_level* level, int on);
+pfsh_status pfsh_profile_read(pfsh_level* level, int kernel, int* launches, double* total_ms);
+
 /* ---------------------------------------------------------------------------
  * Two-level PFASST on one device (Sec. 5.2).  The n_ts time steps of a block
  * ("processors" P_0..P_{n_ts-1}) and `members` independent ensemble members
@@ -211,6 +230,20 @@ pfsh_status pfsh_pfasst_predict(pfsh_pfasst* ctx, double dt, const void* theta0,
  * value), fine F at node 0. */
 pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
                                 int last, void* stream);
+
+/* Swap the context's fine and coarse levels for levels of the same geometry
+ * (T, nlat, nlon, n_nodes, device; max_batch large enough), e.g. levels of
+ * another transform precision: later calls use the new levels, the state
+ * arrays are kept.  Used to finish a block with FP64 fine sweeps after
+ * iterations with mixed-precision transforms. */
+pfsh_status pfsh_pfasst_set_levels(pfsh_pfasst* ctx, pfsh_level* fine, pfsh_level* coarse);
+
+/* When on, pfsh_pfasst_iterate captures the kernel sequence of an iteration
+ * on its stream into a HIP graph the first time it sees a given (arrays, dt,
+ * last, levels, stream) and replays it afterwards.  Needs a non-null stream
+ * that is not already being captured; otherwise the kernels are launched
+ * directly.  Turning it off synchronizes the device and frees the graphs. */
+pfsh_status pfsh_pfasst_set_graphs(pfsh_pfasst* ctx, int on);
 
 #ifdef __cplusplus
 }

@@ -64,6 +64,7 @@ class PfasstResult:
         self.theta = None          # [n_ts][Mf+1, 3, Kf] final fine solution
         self.end_values = []       # per iteration: [n_ts, 3, Kf] fine last-node values after step A
         self.pred_end = None       # [n_ts, 3, Kf] fine last-node values after the predictor
+        self.after_iter = []       # per non-final iteration: [n_ts, Mf+1, 3, Kf] fine state after D
 
 
 def _eval_all(lv, th, lin):
@@ -145,5 +146,6 @@ def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False)
                 inc0 = transfer.zero_pad(th_c[n][0] - transfer.truncate(rcv, Tf, Tc), Tc, Tf)
                 th_f[n][0] = rcv + inc0
             fe_f[n][0], fi_f[n][0] = swe.rhs(lv_f, th_f[n][0], lin)
+        res.after_iter.append(np.array(th_f))
     res.theta = th_f
     return res

@@ -37,11 +37,24 @@ namespace pfsh {
 // apart; outputs spaced fes / fis apart.
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s) {
-  PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
+  {
+    ProfScope p(lv, PFSH_K_PREP, s);
+    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
+  }
   if (!fe) return hipSuccess;
-  PFSH_TRY(launch_leg_synth(lv, 2 * 4 * batch, 4, s));
-  PFSH_TRY(launch_ring_rhs(lv, batch, s));
-  PFSH_TRY(launch_leg_anal(lv, 2 * 5 * batch, 5, s));
+  {
+    ProfScope p(lv, PFSH_K_LEG_SYNTH, s);
+    PFSH_TRY(launch_leg_synth(lv, 2 * 4 * batch, 4, s));
+  }
+  {
+    ProfScope p(lv, PFSH_K_RING, s);
+    PFSH_TRY(launch_ring_rhs(lv, batch, s));
+  }
+  {
+    ProfScope p(lv, PFSH_K_LEG_ANAL, s);
+    PFSH_TRY(launch_leg_anal(lv, 2 * 5 * batch, 5, s));
+  }
+  ProfScope p(lv, PFSH_K_ASSEMBLE, s);
   return launch_assemble(lv, fe, fes, batch, s);
 }
 
@@ -50,9 +63,15 @@ hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, d
                       const double* tau, int batch, hipStream_t s) {
   const long long n3k = 3LL * lv->K;
   const long long stride = lv->nn * n3k;
-  PFSH_TRY(launch_sweep_pre(lv, dt, th, fe, fi, tau, batch, s));
+  {
+    ProfScope p(lv, PFSH_K_SWEEP_PRE, s);
+    PFSH_TRY(launch_sweep_pre(lv, dt, th, fe, fi, tau, batch, s));
+  }
   for (int i = 1; i <= lv->M; ++i) {
-    PFSH_TRY(launch_sweep_node(lv, i, dt, th, fe, fi, batch, s));
+    {
+      ProfScope p(lv, PFSH_K_SWEEP_NODE, s);
+      PFSH_TRY(launch_sweep_node(lv, i, dt, th, fe, fi, batch, s));
+    }
     PFSH_TRY(rhs_strided(lv, th + 2 * i * n3k, stride, fe + 2 * i * n3k, stride, nullptr, 0, batch, s));
   }
   return hipSuccess;
@@ -196,4 +215,40 @@ extern "C" pfsh_status pfsh_fas_tau(const pfsh_level* f, const pfsh_level* c, do
   return st_of(launch_fas_tau(f, c, dt, (const double*)fe_f, (const double*)fi_f,
                               (const double*)fe_c, (const double*)fi_c, (double*)tau_c, batch,
                               (hipStream_t)stream));
+}
+
+static void prof_clear(pfsh_level* lv) {
+  for (auto& v : lv->prof) {
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    v.clear();
+  }
+}
+
+extern "C" pfsh_status pfsh_profile_enable(pfsh_level* lv, int on) {
+  if (!lv) return PFSH_EINVAL;
+  DeviceGuard g(lv->device);
+  if (on) {
+    (void)hipDeviceSynchronize();
+    prof_clear(lv);
+  }
+  lv->prof_on = on != 0;
+  return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_profile_read(pfsh_level* lv, int kernel, int* launches, double* total_ms) {
+  if (!lv || kernel < 0 || kernel >= PFSH_K_COUNT) return PFSH_EINVAL;
+  DeviceGuard g(lv->device);
+  double sum = 0.0;
+  for (auto& pr : lv->prof[kernel]) {
+    if (hipEventSynchronize(pr.second) != hipSuccess) return PFSH_EHIP;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return PFSH_EHIP;
+    sum += ms;
+  }
+  if (launches) *launches = (int)lv->prof[kernel].size();
+  if (total_ms) *total_ms = sum;
+  return PFSH_OK;
 }

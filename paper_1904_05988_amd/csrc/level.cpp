@@ -46,6 +46,11 @@ extern "C" pfsh_status pfsh_level_desc_check(const pfsh_level_desc* d) {
 }
 
 static void free_level(pfsh_level* lv) {
+  for (auto& v : lv->prof)
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   void* ptrs[] = {lv->tabS, lv->tabA, lv->mp_d, lv->itemsS, lv->itemsA, lv->mu_d, lv->w_d,
                   lv->tw_d, lv->eps_d, lv->X, lv->F4, lv->G, lv->Y, lv->S, lv->red};
   for (void* p : ptrs)

@@ -3,6 +3,7 @@
 // the sends and receives of the algorithm are device copies along the batch
 // axis; the coarse step C stays a serial chain over time steps.
 #include <new>
+#include <vector>
 
 #include "pfsh_internal.h"
 
@@ -28,6 +29,17 @@ struct pfsh_pfasst {
   double* tau = nullptr;
   double* base = nullptr;  // predictor: restricted spread initial condition
   double* snap = nullptr;  // fine last-node values sent in step A [B][3][Kf]
+  bool graphs = false;     // replay captured iterations
+  struct Cached {
+    const void *thf, *fef, *fif;
+    const pfsh_level *f, *c;
+    double dt;
+    bool last;
+    hipStream_t s;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<Cached> cache;
 };
 
 namespace {
@@ -38,7 +50,16 @@ namespace {
     if (e_ != hipSuccess) return e_;  \
   } while (0)
 
+void drop_graphs(pfsh_pfasst* x) {
+  for (auto& c : x->cache) {
+    (void)hipGraphExecDestroy(c.x);
+    (void)hipGraphDestroy(c.g);
+  }
+  x->cache.clear();
+}
+
 void free_ctx(pfsh_pfasst* x) {
+  drop_graphs(x);
   double* p[] = {x->thc, x->fec, x->fic, x->tthc, x->tfec, x->tfic, x->tau, x->base, x->snap};
   for (double* q : p)
     if (q) (void)hipFree(q);
@@ -199,6 +220,37 @@ extern "C" pfsh_status pfsh_pfasst_predict(pfsh_pfasst* x, double dt, const void
   return e == hipSuccess ? PFSH_OK : PFSH_EHIP;
 }
 
+// One iteration, replayed from a captured graph when graphs are on and the
+// stream is an ordinary (non-null, not already capturing) stream.
+static hipError_t iterate_maybe_graph(pfsh_pfasst* x, double dt, double* thf, double* fef,
+                                      double* fif, bool last, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool can = x->graphs && s != nullptr && !x->f->prof_on && !x->c->prof_on &&
+                   hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+  if (!can) return iterate(x, dt, thf, fef, fif, last, s);
+  for (auto& c : x->cache)
+    if (c.thf == thf && c.fef == fef && c.fif == fif && c.f == x->f && c.c == x->c && c.dt == dt &&
+        c.last == last && c.s == s)
+      return hipGraphLaunch(c.x, s);
+  PF_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = iterate(x, dt, thf, fef, fif, last, s);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipErrorUnknown);
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return e;
+  }
+  x->cache.push_back({thf, fef, fif, x->f, x->c, dt, last, s, g, ex});
+  return hipGraphLaunch(ex, s);
+}
+
 extern "C" pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* x, double dt, void* theta_f, void* fe_f,
                                            void* fi_f, int last, void* stream) {
   if (!x || !theta_f || !fe_f || !fi_f) return PFSH_EINVAL;
@@ -206,8 +258,36 @@ extern "C" pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* x, double dt, void* thet
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(x->f->device);
-  hipError_t e = iterate(x, dt, (double*)theta_f, (double*)fe_f, (double*)fi_f, last != 0,
-                         (hipStream_t)stream);
+  hipError_t e = iterate_maybe_graph(x, dt, (double*)theta_f, (double*)fe_f, (double*)fi_f,
+                                     last != 0, (hipStream_t)stream);
   (void)hipSetDevice(prev);
   return e == hipSuccess ? PFSH_OK : PFSH_EHIP;
+}
+
+static bool same_geometry(const pfsh_level* a, const pfsh_level* b) {
+  return a->T == b->T && a->nlat == b->nlat && a->nlon == b->nlon && a->nn == b->nn &&
+         a->device == b->device;
+}
+
+extern "C" pfsh_status pfsh_pfasst_set_levels(pfsh_pfasst* x, pfsh_level* fine, pfsh_level* coarse) {
+  if (!x || !fine || !coarse) return PFSH_EINVAL;
+  if (!same_geometry(x->f, fine) || !same_geometry(x->c, coarse)) return PFSH_ESHAPE;
+  if (x->B > fine->d.max_batch || x->B > coarse->d.max_batch) return PFSH_ESHAPE;
+  x->f = fine;
+  x->c = coarse;
+  return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_pfasst_set_graphs(pfsh_pfasst* x, int on) {
+  if (!x) return PFSH_EINVAL;
+  if (!on) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(x->f->device);
+    (void)hipDeviceSynchronize();
+    drop_graphs(x);
+    (void)hipSetDevice(prev);
+  }
+  x->graphs = on != 0;
+  return PFSH_OK;
 }

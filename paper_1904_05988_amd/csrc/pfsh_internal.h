@@ -84,9 +84,31 @@ struct pfsh_level {
   double* red = nullptr;   // residual partial maxima
   size_t red_len = 0;
   size_t bytes_tables = 0, bytes_work = 0;
+  // diagnostic kernel timing (pfsh_profile_*)
+  mutable bool prof_on = false;
+  mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[PFSH_K_COUNT];
 };
 
 namespace pfsh {
+
+// Event bracket of one launch when profiling is on: begin() records the start
+// event before the launch, end() the stop event after it.
+struct ProfScope {
+  const pfsh_level* lv;
+  int id;
+  hipStream_t s;
+  hipEvent_t b = nullptr, e = nullptr;
+  ProfScope(const pfsh_level* l, int k, hipStream_t st) : lv(l), id(k), s(st) {
+    if (!lv->prof_on) return;
+    if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) { b = e = nullptr; return; }
+    (void)hipEventRecord(b, s);
+  }
+  ~ProfScope() {
+    if (!b) return;
+    (void)hipEventRecord(e, s);
+    lv->prof[id].push_back({b, e});
+  }
+};
 
 // ------------------------------------------------------------- host tables
 void gauss_legendre(int nlat, std::vector<double>& mu, std::vector<double>& w);

@@ -53,10 +53,14 @@ _SIGS = {
     "pfsh_restrict": ([_P, _P, _P, _P, _I, _P], _I),
     "pfsh_interpolate_add": ([_P, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_fas_tau": ([_P, _P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
+    "pfsh_profile_enable": ([_P, _I], _I),
+    "pfsh_profile_read": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "pfsh_pfasst_create": ([_P, _P, _I, _I, ctypes.POINTER(_P)], _I),
     "pfsh_pfasst_destroy": ([_P], None),
     "pfsh_pfasst_predict": ([_P, _D, _P, _P, _P, _P, _P], _I),
     "pfsh_pfasst_iterate": ([_P, _D, _P, _P, _P, _I, _P], _I),
+    "pfsh_pfasst_set_levels": ([_P, _P, _P], _I),
+    "pfsh_pfasst_set_graphs": ([_P, _I], _I),
 }
 
 _lib = None
@@ -152,6 +156,19 @@ class Level:
             self.close()
         except Exception:
             pass
+
+    # -- diagnostic kernel timing
+    KERNELS = {"leg_synth": 0, "ring": 1, "leg_anal": 2, "assemble": 3, "prep": 4,
+               "sweep_node": 5, "sweep_pre": 6}
+
+    def profile(self, on=True):
+        _check(lib().pfsh_profile_enable(self._h, int(bool(on))), "pfsh_profile_enable")
+
+    def profile_read(self, kernel):
+        n, ms = ctypes.c_int(), ctypes.c_double()
+        _check(lib().pfsh_profile_read(self._h, self.KERNELS[kernel], ctypes.byref(n),
+                                       ctypes.byref(ms)), "pfsh_profile_read")
+        return n.value, ms.value
 
     # -- allocation helpers (caller-owned device memory)
     def state(self, batch):
@@ -307,6 +324,15 @@ class Pfasst:
 
     def _fine(self, t, n):
         return _need(t, C128, (self.B, self.fine.n_nodes, 3, self.fine.K), n)
+
+    def set_levels(self, fine, coarse):
+        """Continue with levels of the same geometry (e.g. another precision)."""
+        _check(lib().pfsh_pfasst_set_levels(self._h, fine.handle, coarse.handle),
+               "pfsh_pfasst_set_levels")
+        self.fine, self.coarse = fine, coarse
+
+    def set_graphs(self, on=True):
+        _check(lib().pfsh_pfasst_set_graphs(self._h, int(bool(on))), "pfsh_pfasst_set_graphs")
 
     def predict(self, dt, theta0, theta_f, fe_f, fi_f):
         _need(theta0, C128, (self.members, 3, self.fine.K), "theta0")
