@@ -20,50 +20,130 @@
 
 namespace pfsh {
 
-template <class Op>
-__global__ __launch_bounds__(256) void k_leg_synth(const void* __restrict__ tab,
-                                                  const void* __restrict__ X,
-                                                  typename Op::R* __restrict__ F4,
-                                                  const MPInfo* __restrict__ mpi,
-                                                  const WorkItem* __restrict__ items, int RB,
-                                                  int CBs, int CBn, int ncols, int nf, int J,
-                                                  int L) {
-  const WorkItem it = items[blockIdx.x];
-  const MPInfo q = mpi[it.mp];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rb0 = it.tile * 4 + (wave >> 1) * 2;
-  const int cb0 = blockIdx.y * 4 + (wave & 1) * 2;
-  if (rb0 >= RB || cb0 >= CBn) return;  // whole wave idle (no barriers in this kernel)
-  const bool r1 = rb0 + 1 < RB, c1 = cb0 + 1 < CBn;
-  typename Op::C acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-  long long ta = q.tabS + rb0;
-  long long xb = q.xS + cb0;
-  for (int kb = 0; kb < q.kbS; ++kb, ta += RB, xb += CBs) {
-    typename Op::A a0 = Op::load(tab, ta, lane);
-    typename Op::A b0 = Op::load(X, xb, lane);
-    typename Op::A a1 = r1 ? Op::load(tab, ta + 1, lane) : Op::zero();
-    typename Op::A b1 = c1 ? Op::load(X, xb + 1, lane) : Op::zero();
-    acc00 = Op::mma(a0, b0, acc00);
-    if (c1) acc01 = Op::mma(a0, b1, acc01);
-    if (r1) acc10 = Op::mma(a1, b0, acc10);
-    if (r1 && c1) acc11 = Op::mma(a1, b1, acc11);
-  }
-  auto put = [&](const typename Op::C& acc, int rb, int cb) {
-    const int c = cb * 16 + (lane & 15);
-    if (c >= ncols) return;
-    const int ri = c & 1, bf = c >> 1, f = bf % nf, b = bf / nf;
+// K loop of one wave's 2x2 blocks: A blocks at ta, ta+1 (+astep per k-block),
+// B blocks at tb, tb+1 (+bstep).  Operands are loaded PF k-blocks ahead into a
+// register ring, so the memory latency overlaps PF k-blocks of matrix work.
+template <class Op, int PF>
+__device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void* __restrict__ B,
+                                         long long ta, long long astep, long long tb,
+                                         long long bstep, int nk, bool r1, bool c1, int lane,
+                                         typename Op::C& acc00, typename Op::C& acc01,
+                                         typename Op::C& acc10, typename Op::C& acc11) {
+  typename Op::A a0[PF], a1[PF], b0[PF], b1[PF];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = rb * 16 + Op::row(lane, v);
-      if (j < J)
-        F4[(((((size_t)b * J + j) * nf + f) * 2 + q.p) * L + q.m) * 2 + ri] =
-            (typename Op::R)acc[v];
+  for (int s = 0; s < PF; ++s) {
+    const bool ok = s < nk;
+    a0[s] = ok ? Op::load(A, ta + s * astep, lane) : Op::zero();
+    b0[s] = ok ? Op::load(B, tb + s * bstep, lane) : Op::zero();
+    a1[s] = (ok && r1) ? Op::load(A, ta + s * astep + 1, lane) : Op::zero();
+    b1[s] = (ok && c1) ? Op::load(B, tb + s * bstep + 1, lane) : Op::zero();
+  }
+  for (int k0 = 0; k0 < nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      const int kb = k0 + s;
+      if (kb < nk) {
+        acc00 = Op::mma(a0[s], b0[s], acc00);
+        if (c1) acc01 = Op::mma(a0[s], b1[s], acc01);
+        if (r1) acc10 = Op::mma(a1[s], b0[s], acc10);
+        if (r1 && c1) acc11 = Op::mma(a1[s], b1[s], acc11);
+        const int kn = kb + PF;
+        if (kn < nk) {
+          a0[s] = Op::load(A, ta + kn * astep, lane);
+          b0[s] = Op::load(B, tb + kn * bstep, lane);
+          if (r1) a1[s] = Op::load(A, ta + kn * astep + 1, lane);
+          if (c1) b1[s] = Op::load(B, tb + kn * bstep + 1, lane);
+        }
+      }
     }
-  };
-  put(acc00, rb0, cb0);
-  if (c1) put(acc01, rb0, cb0 + 1);
-  if (r1) put(acc10, rb0 + 1, cb0);
-  if (r1 && c1) put(acc11, rb0 + 1, cb0 + 1);
+  }
+}
+
+template <class Op>
+struct Prefetch {
+  static constexpr int depth = Op::KIND == OP_BF16X3 ? 2 : 4;
+};
+
+// Block id -> (work item, column tile), XCD-aware: the hardware deals
+// consecutive block ids to the 8 XCDs in turn, so item i goes to XCD i % 8 and
+// all column tiles of an item run on that XCD back to back, sharing its table
+// and operand lines in that XCD's L2.  Items keep their heaviest-first order.
+__device__ __forceinline__ bool xcd_tile(int nitems, int nct, int& item, int& ct) {
+  const int L = blockIdx.x, xcd = L & 7, r = L >> 3;
+  ct = r % nct;
+  item = (r / nct) * 8 + xcd;
+  return item < nitems;
+}
+
+template <typename R, int MC>
+__device__ __forceinline__ void store_run(R* dst, const R* v) {
+  if constexpr (sizeof(R) == 4) {
+#pragma unroll
+    for (int h = 0; h < MC; h += 4)
+      *reinterpret_cast<float4*>(dst + h) = make_float4(v[h], v[h + 1], v[h + 2], v[h + 3]);
+  } else {
+#pragma unroll
+    for (int h = 0; h < MC; h += 2)
+      *reinterpret_cast<double2*>(dst + h) = make_double2(v[h], v[h + 1]);
+  }
+}
+
+// One workgroup: MC consecutive orders m0..m0+MC-1 of one parity, a tile of
+// 32 rings x 32 columns; wave w computes order m0 + w (2x2 MFMA blocks).  The
+// waves then exchange their tiles through LDS so that every thread stores the
+// MC consecutive-m complex values of one (ring, field) as one contiguous run
+// (64 bytes) in the [slice][ring][field][parity][m] layout the ring stage reads.
+template <class Op, int MC>
+__global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ tab,
+                                                      const void* __restrict__ X,
+                                                      typename Op::R* __restrict__ F4,
+                                                      const MPInfo* __restrict__ mpi,
+                                                      const WorkItem* __restrict__ items,
+                                                      int nitems, int nct, int RB, int CBs,
+                                                      int CBn, int ncols, int nf, int J, int T,
+                                                      int Lp) {
+  typedef typename Op::R R;
+  constexpr int SM = MC + 1;                  // padded m-stride of the LDS tile
+  __shared__ R stage[32 * 32 * SM];           // [row][column][m]
+  int item, ct;
+  if (!xcd_tile(nitems, nct, item, ct)) return;
+  const WorkItem it = items[item];
+  const int p = it.mp & 1, m0 = it.mp >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb0 = it.tile * 2, cb0 = ct * 2;
+  const bool r1 = rb0 + 1 < RB, c1 = cb0 + 1 < CBn;
+  const int m = m0 + wave;
+  typename Op::C acc[4] = {};
+  if (m <= T) {
+    const MPInfo q = mpi[2 * m + p];
+    mma_loop<Op, Prefetch<Op>::depth>(tab, X, q.tabS + rb0, (long long)RB, q.xS + cb0,
+                                      (long long)CBs, q.kbS, r1, c1, lane, acc[0], acc[1],
+                                      acc[2], acc[3]);
+  }
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int rr = (blk >> 1) * 16, cc = (blk & 1) * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] = (R)acc[blk][v];
+  }
+  __syncthreads();
+  // 32 rows x 16 complex columns, MC complex values each
+  for (int t = threadIdx.x; t < 32 * 16; t += 64 * MC) {
+    const int r = t >> 4, cp = t & 15;
+    const int j = rb0 * 16 + r, c = cb0 * 16 + 2 * cp;
+    if (j >= J || c >= ncols) continue;
+    const int bf = c >> 1, f = bf % nf, b = bf / nf;
+    R out[2 * MC];
+    const R* re = stage + (r * 32 + 2 * cp) * SM;
+    const R* im = re + SM;
+#pragma unroll
+    for (int mi = 0; mi < MC; ++mi) {
+      out[2 * mi] = re[mi];
+      out[2 * mi + 1] = im[mi];
+    }
+    store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
+  }
 }
 
 template <class Op>
@@ -71,28 +151,22 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
                                                  const void* __restrict__ G,
                                                  typename Op::R* __restrict__ Y,
                                                  const MPInfo* __restrict__ mpi,
-                                                 const WorkItem* __restrict__ items, int kb2,
-                                                 int CBa, int CBn, int ncols, int Kx, int T) {
-  const WorkItem it = items[blockIdx.x];
+                                                 const WorkItem* __restrict__ items, int nitems,
+                                                 int nct, int kb2, int CBa, int CBn, int ncols,
+                                                 int Kx, int T) {
+  int item, ct;
+  if (!xcd_tile(nitems, nct, item, ct)) return;
+  const WorkItem it = items[item];
   const MPInfo q = mpi[it.mp];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rb0 = it.tile * 4 + (wave >> 1) * 2;
-  const int cb0 = blockIdx.y * 4 + (wave & 1) * 2;
+  const int cb0 = ct * 4 + (wave & 1) * 2;
   if (rb0 >= q.rbA || cb0 >= CBn) return;
   const bool r1 = rb0 + 1 < q.rbA, c1 = cb0 + 1 < CBn;
   typename Op::C acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-  long long ta = q.tabA + rb0;
-  long long gb = (long long)it.mp * kb2 * CBa + cb0;
-  for (int kb = 0; kb < kb2; ++kb, ta += q.rbA, gb += CBa) {
-    typename Op::A a0 = Op::load(tab, ta, lane);
-    typename Op::A b0 = Op::load(G, gb, lane);
-    typename Op::A a1 = r1 ? Op::load(tab, ta + 1, lane) : Op::zero();
-    typename Op::A b1 = c1 ? Op::load(G, gb + 1, lane) : Op::zero();
-    acc00 = Op::mma(a0, b0, acc00);
-    if (c1) acc01 = Op::mma(a0, b1, acc01);
-    if (r1) acc10 = Op::mma(a1, b0, acc10);
-    if (r1 && c1) acc11 = Op::mma(a1, b1, acc11);
-  }
+  mma_loop<Op, Prefetch<Op>::depth>(tab, G, q.tabA + rb0, (long long)q.rbA,
+                                    (long long)it.mp * kb2 * CBa + cb0, (long long)CBa, kb2, r1,
+                                    c1, lane, acc00, acc01, acc10, acc11);
   const int base = ext_off(T, q.m);
   auto put = [&](const typename Op::C& acc, int rb, int cb) {
     const int c = cb * 16 + (lane & 15);
@@ -110,23 +184,26 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
   if (r1 && c1) put(acc11, rb0 + 1, cb0 + 1);
 }
 
+static inline unsigned xcd_grid(int nitems, int nct) {
+  return (unsigned)(((nitems + 7) / 8) * 8 * nct);
+}
+
 template <class Op>
 static hipError_t synth_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
-  const int CBn = (ncols + 15) / 16;
-  dim3 grid(lv->nitemsS, (CBn + 3) / 4);
-  hipLaunchKernelGGL(k_leg_synth<Op>, grid, dim3(256), 0, s, lv->tabS, lv->X,
-                     (typename Op::R*)lv->F4, lv->mp_d, lv->itemsS, lv->RB, lv->CBs, CBn, ncols,
-                     nf, lv->J, lv->L);
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2;
+  constexpr int MC = Op::KIND == OP_F64 ? 4 : 8;
+  hipLaunchKernelGGL((k_leg_synth<Op, MC>), dim3(xcd_grid(lv->nitemsS, nct)), dim3(64 * MC), 0, s,
+                     lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d, lv->itemsS, lv->nitemsS,
+                     nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J, lv->T, lv->Lp);
   return hipGetLastError();
 }
 
 template <class Op>
 static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
-  const int CBn = (ncols + 15) / 16;
-  dim3 grid(lv->nitemsA, (CBn + 3) / 4);
-  hipLaunchKernelGGL(k_leg_anal<Op>, grid, dim3(256), 0, s, lv->tabA, lv->G,
-                     (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->kb2, lv->CBa, CBn, ncols,
-                     lv->Kx, lv->T);
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
+  hipLaunchKernelGGL(k_leg_anal<Op>, dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s, lv->tabA,
+                     lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA, nct,
+                     lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
   return hipGetLastError();
 }
 

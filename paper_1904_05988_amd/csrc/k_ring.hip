@@ -4,9 +4,11 @@
 //
 // Two real rings are carried as one complex signal (north in the real part,
 // south in the imaginary part), so a length-nlon complex FFT transforms both.
-// The FFT is a self-sorting (Stockham) radix-4/2/3 transform: at every stage
-// each thread reads its butterflies' inputs into registers, the workgroup
-// synchronizes, and the outputs are written back in place.
+// The FFT is a self-sorting (Stockham) transform with radix-16 stages first
+// (then 8/4/2 and a final radix 3): at every stage each thread reads its
+// butterflies' inputs into registers, the workgroup synchronizes, and the
+// outputs are written back in place; LDS signals are padded against bank
+// conflicts.
 //
 // k_ring_rhs: Fourier coefficients of Phi', zeta, U = u cos(phi), V = v cos(phi)
 //   (parity form E/O per m) -> grid -> eta = zeta + 2 Omega mu, A = eta U,
@@ -31,9 +33,16 @@ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// radix of stage s for a length-N transform: 4s first, then a 2, then a 3
+// LDS signals are padded by one element every 16 so that the strided
+// accesses of the Stockham stages spread over the banks.
+__host__ __device__ constexpr int padded(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
+
+// radix of stage s for a length-N transform: 16s first, then 8, 4, 2, then a 3
 __host__ __device__ constexpr int radix_of(int N, int s) {
   int n = N, st = 0;
+  while (n % 16 == 0) { if (st == s) return 16; n /= 16; ++st; }
+  while (n % 8 == 0) { if (st == s) return 8; n /= 8; ++st; }
   while (n % 4 == 0) { if (st == s) return 4; n /= 4; ++st; }
   while (n % 2 == 0) { if (st == s) return 2; n /= 2; ++st; }
   while (n % 3 == 0) { if (st == s) return 3; n /= 3; ++st; }
@@ -45,6 +54,29 @@ __host__ __device__ constexpr int nstages(int N) {
   return s;
 }
 
+// e^{SIGN 2 pi i k / 16}
+template <int SIGN, typename R>
+__device__ __forceinline__ cpx<R> w16(int k) {
+  constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                            0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                            -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                            0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  return {(R)c[k & 15], (R)(SIGN * c[(k + 12) & 15])};
+}
+
+template <int SIGN, typename R>
+__device__ __forceinline__ void bfly4(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {
+  cpx<R> s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3, d13 = a1 - a3;
+  cpx<R> jd = {-(R)SIGN * d13.y, (R)SIGN * d13.x};
+  a0 = s02 + s13;
+  a1 = d02 + jd;
+  a2 = s02 - s13;
+  a3 = d02 - jd;
+}
+
+// In-register DFT of length RAD: y[k] = sum_p a[p] e^{SIGN 2 pi i p k / RAD}.
+// RAD = R1 R2 is split as a[q + R1 p] -> inner length-R2 DFTs over p, twiddles
+// e^{SIGN 2 pi i q s / RAD}, outer length-R1 DFTs over q, y[s + R2 t].
 template <int RAD, int SIGN, typename R>
 __device__ __forceinline__ void butterfly(cpx<R>* a) {
   if constexpr (RAD == 2) {
@@ -59,32 +91,61 @@ __device__ __forceinline__ void butterfly(cpx<R>* a) {
     a[0] = a[0] + t;
     a[1] = m + r;
     a[2] = m - r;
-  } else {
-    cpx<R> s02 = a[0] + a[2], d02 = a[0] - a[2], s13 = a[1] + a[3], d13 = a[1] - a[3];
-    cpx<R> jd = {-(R)SIGN * d13.y, (R)SIGN * d13.x};
-    a[0] = s02 + s13;
-    a[1] = d02 + jd;
-    a[2] = s02 - s13;
-    a[3] = d02 - jd;
+  } else if constexpr (RAD == 4) {
+    bfly4<SIGN>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (RAD == 8) {
+    // R1 = 2, R2 = 4
+    bfly4<SIGN>(a[0], a[2], a[4], a[6]);
+    bfly4<SIGN>(a[1], a[3], a[5], a[7]);
+    cpx<R> b1[4] = {a[1], cmul(a[3], w16<SIGN, R>(2)), cmul(a[5], w16<SIGN, R>(4)),
+                    cmul(a[7], w16<SIGN, R>(6))};
+    cpx<R> b0[4] = {a[0], a[2], a[4], a[6]};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a[s] = b0[s] + b1[s];
+      a[s + 4] = b0[s] - b1[s];
+    }
+  } else {  // 16: R1 = R2 = 4
+    cpx<R> b[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cpx<R> t0 = a[q], t1 = a[q + 4], t2 = a[q + 8], t3 = a[q + 12];
+      bfly4<SIGN>(t0, t1, t2, t3);
+      b[q][0] = t0;
+      b[q][1] = q ? cmul(t1, w16<SIGN, R>(q)) : t1;
+      b[q][2] = q ? cmul(t2, w16<SIGN, R>(2 * q)) : t2;
+      b[q][3] = q ? cmul(t3, w16<SIGN, R>(3 * q)) : t3;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cpx<R> t0 = b[0][s], t1 = b[1][s], t2 = b[2][s], t3 = b[3][s];
+      bfly4<SIGN>(t0, t1, t2, t3);
+      a[s] = t0;
+      a[s + 4] = t1;
+      a[s + 8] = t2;
+      a[s + 12] = t3;
+    }
   }
 }
 
-// One Stockham stage on NSIG signals of length N stored back to back in buf.
+// One Stockham stage on NSIG padded signals of length N stored back to back
+// in buf (stride padded_len(N)); tw[t] = e^{2 pi i t / N}.
 template <typename R, int N, int RAD, int NSIG, int NT, int SIGN, int NS>
-__device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int NB = N / RAD;
   constexpr int TOT = NB * NSIG;
   constexpr int PER = (TOT + NT - 1) / NT;
   constexpr int STEP = N / (NS * RAD);
+  constexpr int SP = padded_len(N);
   cpx<R> v[PER][RAD];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = threadIdx.x + q * NT;
     if (TOT % NT == 0 || t < TOT) {
       const int sig = t / NB, j = t - sig * NB, k = j % NS;
-      const cpx<R>* b = buf + sig * N;
+      const cpx<R>* b = buf + sig * SP;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[q][r] = b[j + r * NB];
+      for (int r = 0; r < RAD; ++r) v[q][r] = b[padded(j + r * NB)];
       if (NS > 1) {
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
@@ -102,22 +163,39 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict_
     const int t = threadIdx.x + q * NT;
     if (TOT % NT == 0 || t < TOT) {
       const int sig = t / NB, j = t - sig * NB, k = j % NS;
-      cpx<R>* b = buf + sig * N + (j / NS) * NS * RAD + k;
+      cpx<R>* b = buf + sig * SP;
+      const int base = (j / NS) * NS * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) b[r * NS] = v[q][r];
+      for (int r = 0; r < RAD; ++r) b[padded(base + r * NS)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
 template <typename R, int N, int NSIG, int NT, int SIGN, int S = 0, int NS = 1>
-__device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
   if constexpr (S < nstages(N)) {
     constexpr int RAD = radix_of(N, S);
     fft_stage<R, N, RAD, NSIG, NT, SIGN, NS>(buf, tw);
     fft_run<R, N, NSIG, NT, SIGN, S + 1, NS * RAD>(buf, tw);
   }
 }
+
+// Twiddles e^{2 pi i t / N}: staged in LDS for FP32 (small), read through the
+// cache from global memory for FP64.
+template <typename R, int N>
+struct Twiddles {
+  static constexpr bool kLds = sizeof(R) == 4;
+  static constexpr int kLdsElems = kLds ? N : 0;
+  __device__ static __forceinline__ const cpx<R>* setup(cpx<R>* lds, const cpx<R>* __restrict__ g) {
+    if constexpr (kLds) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) lds[i] = g[i];
+      return lds;  // the caller's next __syncthreads publishes the table
+    } else {
+      return g;
+    }
+  }
+};
 
 // Write one complex value (re, im at columns c, c+1) of degree-parity p of
 // order m for ring j into the analysis data operand.
@@ -142,8 +220,8 @@ __device__ __forceinline__ void load_pair(cpx<R>* sig, int N, int m, cpx<R> E, c
   if (m == 0) {
     sig[0] = {xn.x, xs.x};
   } else {
-    sig[m] = {xn.x - xs.y, xn.y + xs.x};
-    sig[N - m] = {xn.x + xs.y, xs.x - xn.y};
+    sig[padded(m)] = {xn.x - xs.y, xn.y + xs.x};
+    sig[padded(N - m)] = {xn.x + xs.y, xs.x - xn.y};
   }
 }
 
@@ -151,7 +229,7 @@ __device__ __forceinline__ void load_pair(cpx<R>* sig, int N, int m, cpx<R> E, c
 template <typename R>
 __device__ __forceinline__ void split_pair(const cpx<R>* sig, int N, int m, cpx<R>& yn,
                                            cpx<R>& ys) {
-  cpx<R> z = sig[m], w = sig[(N - m) % N];
+  cpx<R> z = sig[padded(m)], w = sig[padded((N - m) % N)];
   yn = {(R)0.5 * (z.x + w.x), (R)0.5 * (z.y - w.y)};
   ys = {(R)0.5 * (z.y + w.y), (R)0.5 * (w.x - z.x)};
 }
@@ -161,35 +239,38 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
                                                  void* __restrict__ G,
                                                  const double* __restrict__ mu,
                                                  const double* __restrict__ wq,
-                                                 const cpx<typename Op::R>* __restrict__ tw, int J,
-                                                 int L, int kb2, int CBa, double two_omega) {
+                                                 const cpx<typename Op::R>* __restrict__ twg, int J,
+                                                 int L, int Lp, int kb2, int CBa, double two_omega) {
   typedef typename Op::R R;
+  constexpr int SP = padded_len(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  cpx<R>* twl = buf + 5 * SP;
   constexpr int NT = 256;
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
-  const int T = L - 1;
-  for (int i = tid; i < 4 * N; i += NT) buf[i] = {(R)0, (R)0};
+  const cpx<R>* tw = Twiddles<R, N>::setup(twl, twg);
+  for (int i = tid; i < 4 * SP; i += NT) buf[i] = {(R)0, (R)0};
   __syncthreads();
-  const R* src = F4 + ((size_t)b * J + j) * 4 * 2 * L * 2;
+  const R* src = F4 + ((size_t)b * J + j) * 4 * 2 * Lp * 2;
   for (int i = tid; i < 4 * L; i += NT) {
     const int f = i / L, m = i - f * L;
-    const R* e = src + ((f * 2 + 0) * L + m) * 2;
-    const R* o = src + ((f * 2 + 1) * L + m) * 2;
-    load_pair<R>(buf + f * N, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
+    const R* e = src + ((f * 2 + 0) * Lp + m) * 2;
+    const R* o = src + ((f * 2 + 1) * Lp + m) * 2;
+    load_pair<R>(buf + f * SP, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
   }
   __syncthreads();
   fft_run<R, N, 4, NT, +1>(buf, tw);
   const double muj = mu[j];
   const R fn = (R)(two_omega * muj), fs = -fn;
   for (int k = tid; k < N; k += NT) {
-    const cpx<R> ph = buf[k], ze = buf[N + k], u = buf[2 * N + k], v = buf[3 * N + k];
+    const int pk = padded(k);
+    const cpx<R> ph = buf[pk], ze = buf[SP + pk], u = buf[2 * SP + pk], v = buf[3 * SP + pk];
     const R en = ze.x + fn, es = ze.y + fs;
-    buf[k] = {en * u.x, es * u.y};
-    buf[N + k] = {en * v.x, es * v.y};
-    buf[2 * N + k] = {ph.x * u.x, ph.y * u.y};
-    buf[3 * N + k] = {ph.x * v.x, ph.y * v.y};
-    buf[4 * N + k] = {(R)0.5 * (u.x * u.x + v.x * v.x), (R)0.5 * (u.y * u.y + v.y * v.y)};
+    buf[pk] = {en * u.x, es * u.y};
+    buf[SP + pk] = {en * v.x, es * v.y};
+    buf[2 * SP + pk] = {ph.x * u.x, ph.y * u.y};
+    buf[3 * SP + pk] = {ph.x * v.x, ph.y * v.y};
+    buf[4 * SP + pk] = {(R)0.5 * (u.x * u.x + v.x * v.x), (R)0.5 * (u.y * u.y + v.y * v.y)};
   }
   __syncthreads();
   fft_run<R, N, 5, NT, -1>(buf, tw);
@@ -197,7 +278,7 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
   for (int i = tid; i < 5 * L; i += NT) {
     const int m = i / 5, f = i - m * 5;
     cpx<R> yn, ys;
-    split_pair<R>(buf + f * N, N, m, yn, ys);
+    split_pair<R>(buf + f * SP, N, m, yn, ys);
     const int c = (b * 5 + f) * 2;
     cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
     cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
@@ -205,28 +286,30 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
     put_g<Op>(G, kb2, CBa, m, 0, j, c, gp.x, gp.y);
     put_g<Op>(G, kb2, CBa, m, 1, j, c, gm.x, gm.y);
   }
-  (void)T;
 }
 
-// scalar synthesis: F4 [0][j][nf][2][L] -> grid [nf][nlat][N]
+// scalar synthesis: F4 [0][j][nf][2][Lp] -> grid [nf][nlat][N]
 template <class Op, int N>
 __global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __restrict__ F4,
                                                    double* __restrict__ grid,
-                                                   const cpx<typename Op::R>* __restrict__ tw,
-                                                   int J, int L, int nf) {
+                                                   const cpx<typename Op::R>* __restrict__ twg,
+                                                   int J, int L, int Lp, int nf) {
   typedef typename Op::R R;
+  constexpr int SP = padded_len(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  cpx<R>* twl = buf + 4 * SP;
   constexpr int NT = 256;
   const int j = blockIdx.x, f0 = blockIdx.y * 4, tid = threadIdx.x;
-  for (int i = tid; i < 4 * N; i += NT) buf[i] = {(R)0, (R)0};
+  const cpx<R>* tw = Twiddles<R, N>::setup(twl, twg);
+  for (int i = tid; i < 4 * SP; i += NT) buf[i] = {(R)0, (R)0};
   __syncthreads();
   for (int i = tid; i < 4 * L; i += NT) {
     const int fl = i / L, m = i - fl * L, f = f0 + fl;
     if (f >= nf) continue;
-    const R* e = F4 + ((((size_t)j * nf + f) * 2 + 0) * L + m) * 2;
-    const R* o = F4 + ((((size_t)j * nf + f) * 2 + 1) * L + m) * 2;
-    load_pair<R>(buf + fl * N, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
+    const R* e = F4 + ((((size_t)j * nf + f) * 2 + 0) * Lp + m) * 2;
+    const R* o = F4 + ((((size_t)j * nf + f) * 2 + 1) * Lp + m) * 2;
+    load_pair<R>(buf + fl * SP, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
   }
   __syncthreads();
   fft_run<R, N, 4, NT, +1>(buf, tw);
@@ -234,7 +317,7 @@ __global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __rest
   for (int i = tid; i < 4 * N; i += NT) {
     const int fl = i / N, k = i - fl * N, f = f0 + fl;
     if (f >= nf) continue;
-    const cpx<R> z = buf[i];
+    const cpx<R> z = buf[fl * SP + padded(k)];
     grid[((size_t)f * nlat + j) * N + k] = (double)z.x;
     grid[((size_t)f * nlat + (nlat - 1 - j)) * N + k] = (double)z.y;
   }
@@ -245,20 +328,23 @@ template <class Op, int N>
 __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ grid,
                                                   void* __restrict__ G,
                                                   const double* __restrict__ wq,
-                                                  const cpx<typename Op::R>* __restrict__ tw,
+                                                  const cpx<typename Op::R>* __restrict__ twg,
                                                   int J, int L, int nf, int kb2, int CBa) {
   typedef typename Op::R R;
+  constexpr int SP = padded_len(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  cpx<R>* twl = buf + 4 * SP;
   constexpr int NT = 256;
   const int j = blockIdx.x, f0 = blockIdx.y * 4, tid = threadIdx.x;
   const int nlat = 2 * J;
+  const cpx<R>* tw = Twiddles<R, N>::setup(twl, twg);
   for (int i = tid; i < 4 * N; i += NT) {
     const int fl = i / N, k = i - fl * N, f = f0 + fl;
     cpx<R> z = {(R)0, (R)0};
     if (f < nf)
       z = {(R)grid[((size_t)f * nlat + j) * N + k], (R)grid[((size_t)f * nlat + (nlat - 1 - j)) * N + k]};
-    buf[i] = z;
+    buf[fl * SP + padded(k)] = z;
   }
   __syncthreads();
   fft_run<R, N, 4, NT, -1>(buf, tw);
@@ -267,7 +353,7 @@ __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ gr
     const int m = i / 4, fl = i - m * 4, f = f0 + fl;
     if (f >= nf) continue;
     cpx<R> yn, ys;
-    split_pair<R>(buf + fl * N, N, m, yn, ys);
+    split_pair<R>(buf + fl * SP, N, m, yn, ys);
     cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
     cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
     if (m == 0) { gp.y = 0; gm.y = 0; }
@@ -283,23 +369,24 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
   typedef typename Op::R R;
   const cpx<R>* tw = reinterpret_cast<const cpx<R>*>(lv->tw_d);
   size_t shm;
+  const size_t twl = (size_t)Twiddles<R, N>::kLdsElems * sizeof(cpx<R>);
   if (kind == 0) {
-    shm = (size_t)5 * N * sizeof(cpx<R>);
+    shm = (size_t)5 * padded_len(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((k_ring_rhs<Op, N>), dim3(lv->J, count), dim3(256), shm, s,
-                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->kb2,
+                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->Lp, lv->kb2,
                        lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
-    shm = (size_t)4 * N * sizeof(cpx<R>);
+    shm = (size_t)4 * padded_len(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_synth<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((k_ring_synth<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
-                       (const R*)lv->F4, gout, tw, lv->J, lv->L, count);
+                       (const R*)lv->F4, gout, tw, lv->J, lv->L, lv->Lp, count);
   } else {
-    shm = (size_t)4 * N * sizeof(cpx<R>);
+    shm = (size_t)4 * padded_len(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_anal<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

@@ -49,60 +49,79 @@ template <class Op>
 __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th, long long sstride,
                                                  double* __restrict__ fi, long long fstride,
                                                  void* __restrict__ X, const MPInfo* __restrict__ mpi,
-                                                 int T, int CBs, Phys ph) {
-  const int m = blockIdx.x, b = blockIdx.y;
-  const double* P = th + (size_t)b * sstride * 2;
+                                                 int T, int CBs, int batch, Phys ph) {
+  typedef typename Op::R R;
+  const int m = blockIdx.x, b0 = 2 * blockIdx.y;   // two slices per workgroup: 16 columns
   const int K = (T + 1) * (T + 2) / 2;
   const int off = spec_off(T, m);
   const double ia = 1.0 / ph.a, a2 = ph.a * ph.a;
-  auto psi = [&](const double* base, int n) -> C2 {   // inverse Laplacian of field at (m, n)
-    if (n < m || n > T || n == 0) return {0.0, 0.0};
-    C2 z = ld2(base + 2 * (off + n - m));
-    const double s = -a2 / ((double)n * (n + 1));
-    return {s * z.x, s * z.y};
-  };
-  const double* Pphi = P;
-  const double* Pzeta = P + 2 * K;
-  const double* Pdelta = P + 4 * K;
   for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
-    C2 phi = {0, 0}, zeta = {0, 0};
-    if (n <= T) {
-      phi = ld2(Pphi + 2 * (off + n - m));
-      zeta = ld2(Pzeta + 2 * (off + n - m));
-      if (fi) {
-        const C2 dl = ld2(Pdelta + 2 * (off + n - m));
-        const double lam = -(double)n * (n + 1) / a2;
-        double* F = fi + (size_t)b * fstride * 2;
-        st2(F + 2 * (off + n - m), {-ph.phibar * dl.x + ph.nu * lam * phi.x,
-                                    -ph.phibar * dl.y + ph.nu * lam * phi.y});
-        st2(F + 2 * (K + off + n - m), {ph.nu * lam * zeta.x, ph.nu * lam * zeta.y});
-        st2(F + 2 * (2 * K + off + n - m), {-lam * phi.x + ph.nu * lam * dl.x,
-                                            -lam * phi.y + ph.nu * lam * dl.y});
+    R vals[16];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const int b = b0 + bb;
+      C2 phi = {0, 0}, zeta = {0, 0}, U = {0, 0}, V = {0, 0};
+      if (b < batch) {
+        const double* P = th + (size_t)b * sstride * 2;
+        const double* Pzeta = P + 2 * K;
+        const double* Pdelta = P + 4 * K;
+        auto psi = [&](const double* base, int nn) -> C2 {   // inverse Laplacian at (m, nn)
+          if (nn < m || nn > T || nn == 0) return {0.0, 0.0};
+          C2 z = ld2(base + 2 * (off + nn - m));
+          const double sc = -a2 / ((double)nn * (nn + 1));
+          return {sc * z.x, sc * z.y};
+        };
+        if (n <= T) {
+          phi = ld2(P + 2 * (off + n - m));
+          zeta = ld2(Pzeta + 2 * (off + n - m));
+          if (fi) {
+            const C2 dl = ld2(Pdelta + 2 * (off + n - m));
+            const double lam = -(double)n * (n + 1) / a2;
+            double* F = fi + (size_t)b * fstride * 2;
+            st2(F + 2 * (off + n - m), {-ph.phibar * dl.x + ph.nu * lam * phi.x,
+                                        -ph.phibar * dl.y + ph.nu * lam * phi.y});
+            st2(F + 2 * (K + off + n - m), {ph.nu * lam * zeta.x, ph.nu * lam * zeta.y});
+            st2(F + 2 * (2 * K + off + n - m), {-lam * phi.x + ph.nu * lam * dl.x,
+                                                -lam * phi.y + ph.nu * lam * dl.y});
+          }
+        }
+        if (n == 0) phi.x -= 1.4142135623730950488 * ph.phibar;
+        const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
+        const C2 ps_m = psi(Pzeta, n - 1), ps_p = psi(Pzeta, n + 1), ps_0 = psi(Pzeta, n);
+        const C2 ch_m = psi(Pdelta, n - 1), ch_p = psi(Pdelta, n + 1), ch_0 = psi(Pdelta, n);
+        const double cm = -(double)(n - 1) * e0, cp = (double)(n + 2) * e1;
+        const C2 pst = {cm * ps_m.x + cp * ps_p.x, cm * ps_m.y + cp * ps_p.y};
+        const C2 cht = {cm * ch_m.x + cp * ch_p.x, cm * ch_m.y + cp * ch_p.y};
+        // i m chi = (-m chi.y, m chi.x)
+        U = {ia * (-m * ch_0.y - pst.x), ia * (m * ch_0.x - pst.y)};
+        V = {ia * (-m * ps_0.y + cht.x), ia * (m * ps_0.x + cht.y)};
+      }
+      const C2 v4[4] = {phi, zeta, U, V};
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        vals[bb * 8 + 2 * f] = (R)v4[f].x;
+        vals[bb * 8 + 2 * f + 1] = (R)v4[f].y;
       }
     }
-    if (n == 0) phi.x -= 1.4142135623730950488 * ph.phibar;
-    const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
-    const C2 ps_m = psi(Pzeta, n - 1), ps_p = psi(Pzeta, n + 1), ps_0 = psi(Pzeta, n);
-    const C2 ch_m = psi(Pdelta, n - 1), ch_p = psi(Pdelta, n + 1), ch_0 = psi(Pdelta, n);
-    const double cm = -(double)(n - 1) * e0, cp = (double)(n + 2) * e1;
-    const C2 pst = {cm * ps_m.x + cp * ps_p.x, cm * ps_m.y + cp * ps_p.y};
-    const C2 cht = {cm * ch_m.x + cp * ch_p.x, cm * ch_m.y + cp * ch_p.y};
-    // i m chi = (-m chi.y, m chi.x)
-    const C2 U = {ia * (-m * ch_0.y - pst.x), ia * (m * ch_0.x - pst.y)};
-    const C2 V = {ia * (-m * ps_0.y + cht.x), ia * (m * ps_0.x + cht.y)};
     const int p = (n - m) & 1, i = (n - m) >> 1;
     const MPInfo q = mpi[2 * m + p];
     const int KB = Op::KB;
-    const long long blk0 = q.xS + (long long)(i / KB) * CBs;
+    const long long blk = q.xS + (long long)(i / KB) * CBs + (b0 * 8) / 16;
     const int kk = i % KB;
-    const int e = (Op::KIND == OP_BF16X3) ? (kk & 7) : 0;
-    const int lk = (Op::KIND == OP_BF16X3) ? (kk >> 3) : kk;
-    const C2 vals[4] = {phi, zeta, U, V};
+    if constexpr (Op::KIND == OP_BF16X3) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int c = (b * 4 + f) * 2;
-      Op::store(X, blk0 + c / 16, lk * 16 + (c % 16), e, (typename Op::R)vals[f].x);
-      Op::store(X, blk0 + (c + 1) / 16, lk * 16 + ((c + 1) % 16), e, (typename Op::R)vals[f].y);
+      for (int c = 0; c < 16; ++c) Op::store(X, blk, (kk >> 3) * 16 + c, kk & 7, vals[c]);
+    } else {
+      R* dst = reinterpret_cast<R*>(X) + blk * 64 + kk * 16;   // 16 consecutive lanes
+      if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < 16; c += 4)
+          *reinterpret_cast<float4*>(dst + c) = make_float4(vals[c], vals[c + 1], vals[c + 2], vals[c + 3]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 16; c += 2)
+          *reinterpret_cast<double2*>(dst + c) = make_double2(vals[c], vals[c + 1]);
+      }
     }
   }
 }
@@ -582,19 +601,19 @@ static inline SdcMat sdc_of(const pfsh_level* lv) {
 
 hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long sstride,
                            double* f_impl, long long fstride, int batch, hipStream_t s) {
-  dim3 grid(lv->L, batch);
+  dim3 grid(lv->L, (batch + 1) / 2);
   switch (lv->op) {
     case OP_F64:
       hipLaunchKernelGGL(k_prep_rhs<OpF64>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, phys_of(lv));
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     case OP_F32:
       hipLaunchKernelGGL(k_prep_rhs<OpF32>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, phys_of(lv));
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     default:
       hipLaunchKernelGGL(k_prep_rhs<OpBF3>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, phys_of(lv));
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
   }
   return hipGetLastError();
 }

@@ -90,9 +90,11 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   lv->nlon = d->nlon;
   lv->J = d->nlat / 2;
   lv->Jp = (lv->J + 31) / 32 * 32;
+  lv->Lp = (lv->L + 7) / 8 * 8;
   lv->nn = d->n_nodes;
   lv->M = d->n_nodes - 1;
   lv->KB = op_kb(lv->op);
+  lv->MC = synth_mc(lv->op);
   lv->RB = lv->Jp / 16;
   lv->kb2 = lv->Jp / lv->KB;
   lv->CBs = (2 * 4 * d->max_batch + 15) / 16;
@@ -119,10 +121,14 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   // work lists, heaviest first so that the hardware's in-order dispatch
   // balances the triangular per-m work
   std::vector<std::pair<long long, WorkItem>> ws, wa;
+  for (int m0 = 0; m0 <= lv->T; m0 += lv->MC)
+    for (int p = 0; p < 2; ++p) {
+      const long long work = lv->mp[2 * m0 + p].kbS;   // the chunk's longest order
+      for (int t = 0; t < (lv->RB + 1) / 2; ++t) ws.push_back({work, WorkItem{2 * m0 + p, t}});
+    }
   for (int i = 0; i < 2 * lv->L; ++i) {
     const MPInfo& q = lv->mp[i];
     if (q.np == 0) continue;
-    for (int t = 0; t < (lv->RB + 3) / 4; ++t) ws.push_back({(long long)q.kbS, WorkItem{i, t}});
     for (int t = 0; t < (q.rbA + 3) / 4; ++t)
       wa.push_back({(long long)std::min(4, q.rbA - 4 * t), WorkItem{i, t}});
   }
@@ -162,7 +168,7 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   const size_t bb = (size_t)op_block_bytes(lv->op);
   const int B = d->max_batch;
   const size_t bytesX = (size_t)xS * bb;
-  const size_t bytesF4 = (size_t)B * lv->J * 5 * 2 * lv->L * 2 * rsz;
+  const size_t bytesF4 = (size_t)B * lv->J * 5 * 2 * lv->Lp * 2 * rsz;
   const size_t bytesG = (size_t)2 * lv->L * lv->kb2 * lv->CBa * bb;
   const size_t bytesY = (size_t)B * 5 * lv->Kx * 2 * rsz;
   const size_t bytesS = (size_t)B * lv->M * 3 * lv->K * 16;

@@ -49,9 +49,13 @@ struct MPInfo {
 };
 
 struct WorkItem {      // one workgroup tile of a Legendre contraction
-  int mp;              // (m, p) index
+  int mp;              // (m, p) index; synthesis: first order of the m-chunk, 2 m0 + p
   int tile;            // row tile (64 rows)
 };
+
+// Synthesis orders per workgroup: the Fourier coefficients of MC consecutive m
+// of one ring are contiguous, so each lane pair writes 64 bytes at once.
+__host__ __device__ inline int synth_mc(int op) { return op == OP_F64 ? 4 : 8; }
 
 }  // namespace pfsh
 
@@ -60,6 +64,8 @@ struct pfsh_level {
   int device;
   int op;                  // pfsh::OpKind
   int T, L, K, Kx, J, Jp, nlat, nlon, nn, M;
+  int Lp;                  // m-stride of the Fourier workspace (L rounded up to 8)
+  int MC;                  // orders m per synthesis workgroup (4 FP64, 8 otherwise)
   int KB, RB, kb2;         // k-block, synthesis row blocks (Jp/16), analysis k-blocks (Jp/KB)
   int CBs, CBa;            // column blocks of the synthesis / analysis data operands
   std::vector<pfsh::MPInfo> mp;
