@@ -11,8 +11,10 @@ iteration stops after its fine sweep), then the fine collocation residual.
 "sweeps/s" counts batched fine sweeps (all 16 slices) per second.
 
 The headline block runs the transform stages in mixed precision (FP32 by
-default) and its last two iterations with FP64 fine levels; the same block in
-plain FP64 is timed next to it, and the final states of the two are compared.
+default) and its last four iterations with FP64 fine levels; the same block in
+plain FP64 is timed next to it, and the states of the two are compared after
+every iteration (and against serial FP64 SDC on the same time steps, the
+collocation solution PFASST converges to).
 Iterations are replayed from captured HIP graphs.  The dominant kernel's
 roofline fraction is measured with HIP events around its launches in a second
 pass over the same blocks with direct launches; the oracle is timed on the
@@ -97,32 +99,47 @@ def ring_bytes(T, nlat, rsz, batch):
     return (4 + 5) * 2 * L * J * batch * 2 * rsz
 
 
-def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
-    """K timed PFASST blocks: iterations 1..N_PF-n64 with the `mixed` transform
-    precision, the last n64 with FP64 fine levels (coarse stays `mixed`)."""
+def make_block(args, mixed, n64, pfsh, inputs, torch):
+    """Levels, PFASST context, arrays and the block closure for one precision
+    recipe: fine transforms in `mixed` (FP64 for its last n64 iterations),
+    coarse level in FP64 (its serial chain is latency-bound, not arithmetic-bound)."""
     dev = torch.device("cuda", 0)
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
     B = N_TS
     gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=mixed)
-    gcm = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B, precision=mixed)
+    gc = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B)
     gf64 = gfm if mixed == "fp64" else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
-    pf = pfsh.Pfasst(gfm, gcm, N_TS)
+    pf = pfsh.Pfasst(gfm, gc, N_TS)
     th0 = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to(dev)
     thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
     res = torch.empty((B, 3), dtype=torch.float64, device=dev)
-    stream = torch.cuda.Stream()
-    pf.set_graphs(not profile)
+    k_switch = args.n_pf - n64
 
     def block():
-        pf.set_levels(gfm, gcm)
+        pf.set_levels(gfm, gc)
         pf.predict(DT, th0, thf, fef, fif)
-        for k in range(args.n_pf):
-            if k == args.n_pf - n64:
-                pf.set_levels(gf64, gcm)
-            pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
+        if args.schedule == "wavefront":
+            pf.run(DT, thf, fef, fif, args.n_pf, fine_alt=None if n64 == 0 else gf64,
+                   k_switch=k_switch)
+        else:
+            for k in range(args.n_pf):
+                if k == k_switch:
+                    pf.set_levels(gf64, gc)
+                pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
         gf64.residual(DT, thf, fef, fif, out=res)
 
+    return dict(block=block, pf=pf, levels=(gfm, gc, gf64), arrays=(thf, fef, fif), res=res)
+
+
+def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
+    """K timed PFASST blocks of one precision recipe."""
+    ctx = make_block(args, mixed, n64, pfsh, inputs, torch)
+    pf, block = ctx["pf"], ctx["block"]
+    gfm = ctx["levels"][0]
+    thf, fef, fif = ctx["arrays"]
+    stream = torch.cuda.Stream()
+    pf.set_graphs(not profile)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             block()
@@ -138,39 +155,57 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
         if profile:
             gfm.profile(False)
             prof = {k: gfm.profile_read(k) for k in gfm.KERNELS}
-        # sweep-only time of the batched fine sweep
         s0 = time.perf_counter()
         for _ in range(10):
             gfm.sdc_sweep(DT, thf, fef, fif)
         torch.cuda.synchronize()
         sweep_ms = (time.perf_counter() - s0) * 1e3 / 10
-    final = None
     pf.set_graphs(False)
     pf.close()
-    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, sweep_ms=sweep_ms, resid=res.cpu().numpy(),
-                final=final)
+    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, sweep_ms=sweep_ms)
 
 
-def run_state(args, mixed, n64, torch, pfsh, inputs):
-    """One block from the seeded state; returns the fine last-node values."""
-    dev = torch.device("cuda", 0)
-    Tf, nlf, nof, nnf = FINE
-    Tc, nlc, noc, nnc = COARSE
-    B = N_TS
-    gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=mixed)
-    gcm = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B, precision=mixed)
-    gf64 = gfm if mixed == "fp64" else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
-    pf = pfsh.Pfasst(gfm, gcm, N_TS)
-    th0 = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to(dev)
-    thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
+def run_states(args, mixed, n64, torch, pfsh, inputs):
+    """One block from the seeded state with the iteration schedule (the
+    wavefront order gives bitwise the same states); returns the fine last-node
+    values of all slices after each iteration."""
+    a = argparse.Namespace(**vars(args))
+    a.schedule = "iterations"
+    ctx = make_block(a, mixed, n64, pfsh, inputs, torch)
+    pf, (gfm, gc, gf64) = ctx["pf"], ctx["levels"]
+    thf, fef, fif = ctx["arrays"]
+    th0 = torch.from_numpy(inputs.seeded_state(FINE[0], SEED)[None]).to("cuda")
+    pf.set_levels(gfm, gc)
     pf.predict(DT, th0, thf, fef, fif)
+    out = []
     for k in range(args.n_pf):
         if k == args.n_pf - n64:
-            pf.set_levels(gf64, gcm)
+            pf.set_levels(gf64, gc)
         pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
-    out = thf[:, -1].cpu().numpy()
+        out.append(thf[:, -1].cpu().numpy())
     pf.close()
     return out
+
+
+def serial_reference(torch, pfsh, inputs, nsweeps=20):
+    """Serial FP64 SDC on the fine level, step after step (collocation solution
+    of every time step of the block, to which PFASST converges)."""
+    Tf, nlf, nof, nnf = FINE
+    gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=1)
+    x = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to("cuda")
+    out = []
+    for _ in range(N_TS):
+        th, fe, fi = gl.space_time(1), gl.space_time(1), gl.space_time(1)
+        e, i = gl.rhs(x)
+        th[:, 0] = x
+        fe[:, 0] = e
+        fi[:, 0] = i
+        gl.spread(th, fe, fi)
+        for _ in range(nsweeps):
+            gl.sdc_sweep(DT, th, fe, fi)
+        x = th[:, -1].contiguous()
+        out.append(x[0].cpu().numpy())
+    return np.array(out)
 
 
 def rel_err(a, b):
@@ -227,9 +262,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10, help="timed PFASST blocks")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16x3"])
-    ap.add_argument("--n64", type=int, default=2,
+    ap.add_argument("--n64", type=int, default=4,
                     help="final PFASST iterations with FP64 fine levels in the mixed block")
     ap.add_argument("--n-pf", type=int, default=8, help="PFASST iterations per block")
+    ap.add_argument("--schedule", default="iterations", choices=["wavefront", "iterations"],
+                    help="order of the PFASST work inside a block (same arithmetic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (HBM counter calibration)")
@@ -258,11 +295,15 @@ def main():
     rmx = run_gpu(args, args.mixed, args.n64, torch, pfsh, inputs)
     # the same timed blocks again with direct launches and HIP events per kernel
     rpr = run_gpu(args, args.mixed, args.n64, torch, pfsh, inputs, profile=True)
-    x64 = run_state(args, "fp64", 0, torch, pfsh, inputs)
-    xmx = run_state(args, args.mixed, args.n64, torch, pfsh, inputs)
-    xpure = run_state(args, args.mixed, 0, torch, pfsh, inputs)
+    s64 = run_states(args, "fp64", 0, torch, pfsh, inputs)
+    smx = run_states(args, args.mixed, args.n64, torch, pfsh, inputs)
+    spure = run_states(args, args.mixed, 0, torch, pfsh, inputs)
+    x64, xmx, xpure = s64[-1], smx[-1], spure[-1]
     err = rel_err(xmx, x64)
     err_pure = rel_err(xpure, x64)
+    err_iter = [rel_err(a, b) for a, b in zip(smx, s64)]
+    err_iter_pure = [rel_err(a, b) for a, b in zip(spure, s64)]
+    xref = serial_reference(torch, pfsh, inputs)
 
     # dominant kernel of the mixed-precision fine level and its roofline
     prof = rpr["prof"]
@@ -295,6 +336,7 @@ def main():
         "config": {"workload": "pfasst_t255_t127_16slices", "fine": "T255 384x768 5 Lobatto nodes",
                    "coarse": "T127 192x384 3 nodes", "slices": N_TS, "dt_s": DT,
                    "n_pf": args.n_pf, "fp64_final_iterations": args.n64,
+                   "schedule": args.schedule, "coarse_precision": "fp64",
                    "step": "one PFASST block: predictor + n_pf iterations, fine residual",
                    "seed": SEED, "parallelism": "slices as batch, 1 GPU"},
         "roofline": roof,
@@ -304,6 +346,10 @@ def main():
         "mixed_rel_err_vs_fp64": err,
         "mixed_ok": bool(max(err) <= 1e-6),
         "mixed_without_fp64_iterations_rel_err": err_pure,
+        "mixed_rel_err_per_iteration": err_iter,
+        "mixed_without_fp64_iterations_rel_err_per_iteration": err_iter_pure,
+        "pfasst_err_vs_serial_collocation": {"fp64": rel_err(x64, xref), "mixed": rel_err(xmx, xref),
+                                             "mixed_without_fp64_iterations": rel_err(xpure, xref)},
         "sweep_only_ms": rmx["sweep_ms"],
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},

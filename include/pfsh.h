@@ -231,6 +231,21 @@ pfsh_status pfsh_pfasst_predict(pfsh_pfasst* ctx, double dt, const void* theta0,
 pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
                                 int last, void* stream);
 
+/* n_iter PFASST iterations (the last stopping after its fine sweep) in
+ * wavefront order: super-step t advances every time step n whose iteration
+ * k = t - n lies in [0, n_iter), batched over that contiguous range of steps.
+ * Each step needs only what its left neighbour produced one super-step earlier
+ * (the coarse last-node value of step C, the fine last-node value of step A),
+ * so the serial coarse chains of consecutive iterations overlap: n_ts + n_iter
+ * - 1 super-steps instead of n_iter serial chains of n_ts coarse sweeps.  The
+ * arithmetic is that of n_iter pfsh_pfasst_iterate calls (bitwise for FP64).
+ * If fine_alt is not NULL (same geometry as the fine level), iterations
+ * k >= k_switch sweep on fine_alt, and the step-D re-evaluation of F at node
+ * 0 that precedes them does too.  Replayed from a captured graph when graphs
+ * are on. */
+pfsh_status pfsh_pfasst_run(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
+                            int n_iter, pfsh_level* fine_alt, int k_switch, void* stream);
+
 /* Swap the context's fine and coarse levels for levels of the same geometry
  * (T, nlat, nlon, n_nodes, device; max_batch large enough), e.g. levels of
  * another transform precision: later calls use the new levels, the state

@@ -2,6 +2,7 @@
 // steps and ensemble members are one batch (slice s = step * members + member);
 // the sends and receives of the algorithm are device copies along the batch
 // axis; the coarse step C stays a serial chain over time steps.
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -29,12 +30,15 @@ struct pfsh_pfasst {
   double* tau = nullptr;
   double* base = nullptr;  // predictor: restricted spread initial condition
   double* snap = nullptr;  // fine last-node values sent in step A [B][3][Kf]
+  double* fmail = nullptr; // wavefront: fine last-node values, two super-steps [2][B][3][Kf]
+  double* cmail = nullptr; // wavefront: coarse last-node values [2][B][3][Kc]
   bool graphs = false;     // replay captured iterations
   struct Cached {
     const void *thf, *fef, *fif;
-    const pfsh_level *f, *c;
+    const pfsh_level *f, *c, *alt;
     double dt;
-    bool last;
+    int last;        // iterate: last flag; wavefront run: -(n_iter)
+    int k_switch;
     hipStream_t s;
     hipGraph_t g;
     hipGraphExec_t x;
@@ -60,7 +64,8 @@ void drop_graphs(pfsh_pfasst* x) {
 
 void free_ctx(pfsh_pfasst* x) {
   drop_graphs(x);
-  double* p[] = {x->thc, x->fec, x->fic, x->tthc, x->tfec, x->tfic, x->tau, x->base, x->snap};
+  double* p[] = {x->thc, x->fec, x->fic, x->tthc, x->tfec, x->tfic, x->tau, x->base, x->snap,
+                 x->fmail, x->cmail};
   for (double* q : p)
     if (q) (void)hipFree(q);
   delete x;
@@ -157,6 +162,90 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
   return rhs_strided(x->f, thf, z.stf, fef, z.stf, fif, z.stf, B, s);
 }
 
+// n_iter iterations in wavefront order.  Super-step t advances every step n
+// whose iteration k = t - n lies in [0, n_iter): the work of a super-step is the
+// work of Algorithm 1 on a contiguous range of steps (batched), and each step
+// only needs values its left neighbour produced in super-step t-1 (coarse
+// last-node value after C, fine last-node value after A) or that it produced
+// itself in t-1.  The arithmetic is that of n_iter iterate() calls.
+// Iterations k >= k_switch sweep on `alt` (and the F re-evaluation of step D
+// before such an iteration uses `alt` too).
+hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, double* fif,
+                         int n_iter, const pfsh_level* alt, int k_switch, hipStream_t s) {
+  const Sizes z = sizes(x);
+  const int mem = x->members, Mf = x->f->M, Mc = x->c->M, nts = x->n_ts;
+  if (!alt) k_switch = n_iter;
+  const size_t ff = 2 * (size_t)z.stf, fc = 2 * (size_t)z.stc;   // doubles per step-member slice
+  for (int t = 0; t <= nts + n_iter - 2; ++t) {
+    const int n_lo = std::max(0, t - (n_iter - 1)), n_hi = std::min(t, nts - 1);
+    if (n_lo > n_hi) continue;
+    // A) fine sweeps, split where the iteration index crosses k_switch
+    //    (k = t - n decreases with n, so steps n <= t - k_switch use alt)
+    const int split = std::min(n_hi, t - k_switch);   // last step on alt
+    auto sweep_range = [&](int a, int b, const pfsh_level* lv) -> hipError_t {
+      if (a > b) return hipSuccess;
+      const size_t o = (size_t)a * mem * ff;
+      return sweep_impl(lv, dt, thf + o, fef + o, fif + o, nullptr, (b - a + 1) * mem, s);
+    };
+    PF_TRY(sweep_range(n_lo, split, alt));
+    PF_TRY(sweep_range(std::max(n_lo, split + 1), n_hi, x->f));
+    // steps in their last iteration stop after A
+    const int b_lo = (t - n_lo == n_iter - 1) ? n_lo + 1 : n_lo, b_hi = n_hi;
+    if (b_lo > b_hi) continue;
+    const int nb = (b_hi - b_lo + 1) * mem;
+    const size_t of = (size_t)b_lo * mem * ff, oc = (size_t)b_lo * mem * fc;
+    double* fm_now = x->fmail + (size_t)(t & 1) * x->B * 2 * z.n3kf;
+    double* fm_prev = x->fmail + (size_t)((t + 1) & 1) * x->B * 2 * z.n3kf;
+    double* cm_now = x->cmail + (size_t)(t & 1) * x->B * 2 * z.n3kc;
+    double* cm_prev = x->cmail + (size_t)((t + 1) & 1) * x->B * 2 * z.n3kc;
+    const size_t omf = (size_t)b_lo * mem * 2 * z.n3kf, omc = (size_t)b_lo * mem * 2 * z.n3kc;
+    PF_TRY(launch_copy_state(thf + of + 2 * (size_t)Mf * z.n3kf, z.stf, fm_now + omf, z.n3kf,
+                             z.n3kf, nb, s));
+    // B) restrict, coarse F, saved copies, tau
+    PF_TRY(launch_restrict(x->f, x->c, thf + of, x->thc + oc, nb, s));
+    PF_TRY(eval_all(x->c, x->thc + oc, x->fec + oc, x->fic + oc, nb, s));
+    PF_TRY(launch_copy_state(x->thc + oc, z.stc, x->tthc + oc, z.stc, z.stc, nb, s));
+    PF_TRY(launch_copy_state(x->fec + oc, z.stc, x->tfec + oc, z.stc, z.stc, nb, s));
+    PF_TRY(launch_copy_state(x->fic + oc, z.stc, x->tfic + oc, z.stc, z.stc, nb, s));
+    PF_TRY(launch_fas_tau(x->f, x->c, dt, fef + of, fif + of, x->fec + oc, x->fic + oc,
+                          x->tau + oc, nb, s));
+    // C) coarse initial conditions from the left neighbours (super-step t-1),
+    //    coarse F at node 0, coarse sweeps, send
+    const int r_lo = std::max(b_lo, 1);
+    if (r_lo <= b_hi) {
+      const int nr = (b_hi - r_lo + 1) * mem;
+      const size_t ocr = (size_t)r_lo * mem * fc;
+      PF_TRY(launch_copy_state(cm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kc, z.n3kc,
+                               x->thc + ocr, z.stc, z.n3kc, nr, s));
+      PF_TRY(rhs_strided(x->c, x->thc + ocr, z.stc, x->fec + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
+    }
+    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s));
+    PF_TRY(launch_copy_state(x->thc + oc + 2 * (size_t)Mc * z.n3kc, z.stc, cm_now + omc, z.n3kc,
+                             z.n3kc, nb, s));
+    // D) interpolate the coarse increments, new fine initial conditions, fine F
+    //    at node 0 (on the level of the next iteration)
+    PF_TRY(launch_interp_add(x->c, x->f, x->thc + oc, x->tthc + oc, thf + of, nb, s));
+    PF_TRY(launch_interp_add(x->c, x->f, x->fec + oc, x->tfec + oc, fef + of, nb, s));
+    PF_TRY(launch_interp_add(x->c, x->f, x->fic + oc, x->tfic + oc, fif + of, nb, s));
+    if (r_lo <= b_hi) {
+      const int nr = (b_hi - r_lo + 1) * mem;
+      PF_TRY(launch_ic_correct(x->f, x->c, fm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kf, z.n3kf,
+                               x->thc + (size_t)r_lo * mem * fc, z.stc,
+                               thf + (size_t)r_lo * mem * ff, z.stf, nr, s));
+    }
+    // next iteration k+1 = t - n + 1 >= k_switch  <=>  n <= t + 1 - k_switch
+    const int split_d = std::min(b_hi, t + 1 - k_switch);
+    auto f0_range = [&](int a, int b, const pfsh_level* lv) -> hipError_t {
+      if (a > b) return hipSuccess;
+      const size_t o = (size_t)a * mem * ff;
+      return rhs_strided(lv, thf + o, z.stf, fef + o, z.stf, fif + o, z.stf, (b - a + 1) * mem, s);
+    };
+    PF_TRY(f0_range(b_lo, split_d, alt));
+    PF_TRY(f0_range(std::max(b_lo, split_d + 1), b_hi, x->f));
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" pfsh_status pfsh_pfasst_create(pfsh_level* f, pfsh_level* c, int n_ts, int members,
@@ -184,6 +273,8 @@ extern "C" pfsh_status pfsh_pfasst_create(pfsh_level* f, pfsh_level* c, int n_ts
   for (double** p : bufs)
     if (e == hipSuccess) e = hipMalloc((void**)p, bc);
   if (e == hipSuccess) e = hipMalloc((void**)&x->snap, bf);
+  if (e == hipSuccess) e = hipMalloc((void**)&x->fmail, 2 * bf);
+  if (e == hipSuccess) e = hipMalloc((void**)&x->cmail, 2 * (size_t)B * z.n3kc * 16);
   if (e == hipSuccess)
     for (double** p : bufs)
       if (e == hipSuccess) e = hipMemset(*p, 0, bc);
@@ -229,8 +320,8 @@ static hipError_t iterate_maybe_graph(pfsh_pfasst* x, double dt, double* thf, do
                    hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
   if (!can) return iterate(x, dt, thf, fef, fif, last, s);
   for (auto& c : x->cache)
-    if (c.thf == thf && c.fef == fef && c.fif == fif && c.f == x->f && c.c == x->c && c.dt == dt &&
-        c.last == last && c.s == s)
+    if (c.thf == thf && c.fef == fef && c.fif == fif && c.f == x->f && c.c == x->c &&
+        c.alt == nullptr && c.dt == dt && c.last == (int)last && c.k_switch == 0 && c.s == s)
       return hipGraphLaunch(c.x, s);
   PF_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t e = iterate(x, dt, thf, fef, fif, last, s);
@@ -247,8 +338,56 @@ static hipError_t iterate_maybe_graph(pfsh_pfasst* x, double dt, double* thf, do
     (void)hipGraphDestroy(g);
     return e;
   }
-  x->cache.push_back({thf, fef, fif, x->f, x->c, dt, last, s, g, ex});
+  x->cache.push_back({thf, fef, fif, x->f, x->c, nullptr, dt, (int)last, 0, s, g, ex});
   return hipGraphLaunch(ex, s);
+}
+
+static hipError_t run_maybe_graph(pfsh_pfasst* x, double dt, double* thf, double* fef, double* fif,
+                                  int n_iter, const pfsh_level* alt, int k_switch, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool can = x->graphs && s != nullptr && !x->f->prof_on && !x->c->prof_on &&
+                   !(alt && alt->prof_on) && hipStreamIsCapturing(s, &cs) == hipSuccess &&
+                   cs == hipStreamCaptureStatusNone;
+  if (!can) return run_wavefront(x, dt, thf, fef, fif, n_iter, alt, k_switch, s);
+  for (auto& c : x->cache)
+    if (c.thf == thf && c.fef == fef && c.fif == fif && c.f == x->f && c.c == x->c &&
+        c.alt == alt && c.dt == dt && c.last == -n_iter && c.k_switch == k_switch && c.s == s)
+      return hipGraphLaunch(c.x, s);
+  PF_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = run_wavefront(x, dt, thf, fef, fif, n_iter, alt, k_switch, s);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipErrorUnknown);
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return e;
+  }
+  x->cache.push_back({thf, fef, fif, x->f, x->c, alt, dt, -n_iter, k_switch, s, g, ex});
+  return hipGraphLaunch(ex, s);
+}
+
+static bool same_geometry(const pfsh_level* a, const pfsh_level* b);
+
+extern "C" pfsh_status pfsh_pfasst_run(pfsh_pfasst* x, double dt, void* theta_f, void* fe_f,
+                                       void* fi_f, int n_iter, pfsh_level* fine_alt, int k_switch,
+                                       void* stream) {
+  if (!x || !theta_f || !fe_f || !fi_f) return PFSH_EINVAL;
+  if (!(dt > 0) || n_iter < 1) return PFSH_EINVAL;
+  if (fine_alt && (!same_geometry(x->f, fine_alt) || x->B > fine_alt->d.max_batch)) return PFSH_ESHAPE;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(x->f->device);
+  hipError_t e = run_maybe_graph(x, dt, (double*)theta_f, (double*)fe_f, (double*)fi_f, n_iter,
+                                 fine_alt, fine_alt ? std::max(0, k_switch) : n_iter,
+                                 (hipStream_t)stream);
+  (void)hipSetDevice(prev);
+  return e == hipSuccess ? PFSH_OK : PFSH_EHIP;
 }
 
 extern "C" pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* x, double dt, void* theta_f, void* fe_f,

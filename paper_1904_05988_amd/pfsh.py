@@ -59,6 +59,7 @@ _SIGS = {
     "pfsh_pfasst_destroy": ([_P], None),
     "pfsh_pfasst_predict": ([_P, _D, _P, _P, _P, _P, _P], _I),
     "pfsh_pfasst_iterate": ([_P, _D, _P, _P, _P, _I, _P], _I),
+    "pfsh_pfasst_run": ([_P, _D, _P, _P, _P, _I, _P, _I, _P], _I),
     "pfsh_pfasst_set_levels": ([_P, _P, _P], _I),
     "pfsh_pfasst_set_graphs": ([_P, _I], _I),
 }
@@ -324,6 +325,17 @@ class Pfasst:
 
     def _fine(self, t, n):
         return _need(t, C128, (self.B, self.fine.n_nodes, 3, self.fine.K), n)
+
+    def run(self, dt, theta_f, fe_f, fi_f, n_iter, fine_alt=None, k_switch=None):
+        """n_iter iterations in wavefront order (same arithmetic as n_iter
+        iterate() calls, the last one stopping after its fine sweep);
+        iterations >= k_switch use fine_alt for the fine level."""
+        for t, n in ((theta_f, "theta_f"), (fe_f, "fe_f"), (fi_f, "fi_f")):
+            self._fine(t, n)
+        ks = n_iter if k_switch is None else int(k_switch)
+        _check(lib().pfsh_pfasst_run(self._h, float(dt), _ptr(theta_f), _ptr(fe_f), _ptr(fi_f),
+                                     int(n_iter), None if fine_alt is None else fine_alt.handle,
+                                     ks, _stream(theta_f)), "pfsh_pfasst_run")
 
     def set_levels(self, fine, coarse):
         """Continue with levels of the same geometry (e.g. another precision)."""

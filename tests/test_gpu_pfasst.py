@@ -100,3 +100,51 @@ def test_graph_replay_and_level_swap_match_direct_launches():
     with pytest.raises(pfsh.PfshError):
         pf2 = pfsh.Pfasst(gf, gc, n_ts)
         pf2.set_levels(gc, gc)      # wrong geometry for the fine level
+
+
+@pytest.mark.parametrize("n_ts,n_iter,members", [(4, 4, 1), (3, 5, 2), (1, 3, 1), (5, 2, 1)])
+def test_wavefront_run_equals_iteration_order(n_ts, n_iter, members):
+    """The wavefront schedule performs the arithmetic of Algorithm 1 in another
+    order: results equal the iteration-by-iteration calls bit for bit."""
+    import torch
+    Tf, Tc, nf, nc, dt = 15, 7, 5, 3, 300.0
+    B = n_ts * members
+    gf, gc, _, _ = _levels(Tf, Tc, nf, nc, B, (24, 48), (12, 24))
+    th0 = to_dev(seeded(Tf, tuple(range(80, 80 + members))))
+    outs = []
+    stream = torch.cuda.Stream()
+    for mode in ("iterate", "run", "run_graph"):
+        pf = pfsh.Pfasst(gf, gc, n_ts, members)
+        pf.set_graphs(mode == "run_graph")
+        thf, fef, fif = gf.space_time(B), gf.space_time(B), gf.space_time(B)
+        with torch.cuda.stream(stream):
+            for rep in range(2 if mode == "run_graph" else 1):
+                pf.predict(dt, th0, thf, fef, fif)
+                if mode == "iterate":
+                    for k in range(n_iter):
+                        pf.iterate(dt, thf, fef, fif, last=(k == n_iter - 1))
+                else:
+                    pf.run(dt, thf, fef, fif, n_iter)
+            stream.synchronize()
+        outs.append((to_host(thf), to_host(fef), to_host(fif)))
+        pf.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_wavefront_with_fp64_finish_tracks_fp64():
+    Tf, Tc, nf, nc, dt, n_ts = 31, 15, 5, 3, 120.0, 6
+    gf, gc, _, _ = _levels(Tf, Tc, nf, nc, n_ts, (48, 96), (24, 48))
+    gf32 = pfsh.Level(Tf, 48, 96, nf, max_batch=n_ts, precision="fp32")
+    th0 = to_dev(seeded(Tf, (90,)))
+    res = []
+    for fine, alt in ((gf, None), (gf32, gf)):
+        pf = pfsh.Pfasst(fine, gc, n_ts)
+        thf, fef, fif = gf.space_time(n_ts), gf.space_time(n_ts), gf.space_time(n_ts)
+        pf.predict(dt, th0, thf, fef, fif)
+        pf.run(dt, thf, fef, fif, 6, fine_alt=alt, k_switch=4)
+        res.append(to_host(thf)[:, -1])
+        pf.close()
+    err = np.max([rel_err(res[1][n], res[0][n]) for n in range(n_ts)], axis=0)
+    assert np.all(err <= 1e-6), err
