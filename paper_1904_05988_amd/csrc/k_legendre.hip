@@ -115,10 +115,13 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
   const int m = m0 + wave;
   typename Op::C acc[4] = {};
   if (m <= T) {
+    // degrees from the highest down: the coefficients decay with n, so the
+    // small terms are summed before the large low-degree ones
     const MPInfo q = mpi[2 * m + p];
-    mma_loop<Op, Prefetch<Op>::depth>(tab, X, q.tabS + rb0, (long long)RB, q.xS + cb0,
-                                      (long long)CBs, q.kbS, r1, c1, lane, acc[0], acc[1],
-                                      acc[2], acc[3]);
+    const long long last = q.kbS - 1;
+    mma_loop<Op, Prefetch<Op>::depth>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
+                                      q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, r1, c1,
+                                      lane, acc[0], acc[1], acc[2], acc[3]);
   }
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk) {

@@ -54,10 +54,12 @@ def test_t255_b16_sweep_sampled_against_oracle(t255_states):
 
 
 # bounds per variable (Phi, zeta, delta) after two sweeps from the spread guess,
-# normalized per variable: the divergence's high-wavenumber tendencies are
-# amplified by n(n+1) (kinetic-energy Laplacian) and by the curl, so its
-# transform round-off shows most
-SWEEP_BOUNDS = {"fp32": (1e-7, 1e-6, 1e-4), "bf16x3": (2e-6, 1e-5, 1e-3)}
+# each normalized by that slice's own maximum.  The divergence shows transform
+# rounding most: its high-degree tendencies carry the kinetic-energy Laplacian
+# (factor n(n+1)/a^2) and the gravity-wave response to geopotential errors,
+# while its own amplitude is small (down to 3e-7 1/s in seed 303).  Measured
+# on gfx950: FP32 (7e-9, 4.5e-8, 1.9e-5), BF16x3 (3.7e-7, 1.5e-6, 1.1e-3).
+SWEEP_BOUNDS = {"fp32": (2e-8, 2e-7, 5e-5), "bf16x3": (1e-6, 5e-6, 3e-3)}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
