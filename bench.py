@@ -115,6 +115,17 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
     thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
     res = torch.empty((B, 3), dtype=torch.float64, device=dev)
     k_switch = args.n_pf - n64
+    tuned = {}
+    if not getattr(args, "no_tune", False):
+        # the batches each level runs: fine sweeps of all slices (the wavefront
+        # order also smaller groups), coarse batched steps and the serial chain
+        fine_b = [B] if args.schedule == "iterations" else [B, 8, 4, 2, 1]
+        for name, lv, batches in (("fine", gfm, fine_b), ("fine_fp64", gf64, fine_b),
+                                  ("coarse", gc, [1, 2, 4, 8, B])):
+            if name == "fine_fp64" and gf64 is gfm:
+                continue
+            tuned[name] = {b: {k: v[0] for k, v in lv.autotune(b, reps=10).items()} for b in batches}
+        torch.cuda.synchronize()
 
     def block():
         pf.set_levels(gfm, gc)
@@ -129,7 +140,8 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
                 pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
         gf64.residual(DT, thf, fef, fif, out=res)
 
-    return dict(block=block, pf=pf, levels=(gfm, gc, gf64), arrays=(thf, fef, fif), res=res)
+    return dict(block=block, pf=pf, levels=(gfm, gc, gf64), arrays=(thf, fef, fif), res=res,
+                tuned=tuned)
 
 
 def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
@@ -162,7 +174,7 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
         sweep_ms = (time.perf_counter() - s0) * 1e3 / 10
     pf.set_graphs(False)
     pf.close()
-    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, sweep_ms=sweep_ms)
+    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, sweep_ms=sweep_ms, tuned=ctx["tuned"])
 
 
 def run_states(args, mixed, n64, torch, pfsh, inputs):
@@ -171,6 +183,7 @@ def run_states(args, mixed, n64, torch, pfsh, inputs):
     values of all slices after each iteration."""
     a = argparse.Namespace(**vars(args))
     a.schedule = "iterations"
+    a.no_tune = True
     ctx = make_block(a, mixed, n64, pfsh, inputs, torch)
     pf, (gfm, gc, gf64) = ctx["pf"], ctx["levels"]
     thf, fef, fif = ctx["arrays"]
@@ -268,6 +281,8 @@ def main():
     ap.add_argument("--schedule", default="iterations", choices=["wavefront", "iterations"],
                     help="order of the PFASST work inside a block (same arithmetic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default transform-kernel variants (no autotuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -353,6 +368,7 @@ def main():
         "sweep_only_ms": rmx["sweep_ms"],
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
+        "tuned_variants": rmx["tuned"],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -197,6 +197,38 @@ pfsh_status pfsh_profile_enable(pfsh_level* level, int on);
 pfsh_status pfsh_profile_read(pfsh_level* level, int kernel, int* launches, double* total_ms);
 
 /* ---------------------------------------------------------------------------
+ * Transform-kernel variants and the autotuner.  A level launches one variant
+ * of each transform stage per size bucket (the batch of an RHS evaluation,
+ * rounded up to a power of two, after conversion to 16-column MFMA blocks for
+ * the Legendre stages); variant 0 is the built-in default.
+ *   stage 0, Legendre synthesis: prefetch depth of the K loop
+ *            (FP64 / FP32: 4, 2, 8; BF16x3: 2, 4);
+ *   stage 1, Legendre analysis: (prefetch depth, tile shape), shape 0 = 64
+ *            degrees x 64 columns per workgroup, 1 = 64 x 32 with one degree
+ *            block per wave (FP64 / FP32: (4,0) (2,0) (8,0) (4,1) (8,1);
+ *            BF16x3: (2,0) (4,0) (2,1) (4,1));
+ *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4.
+ * The Legendre variants give bitwise identical results (same order of every
+ * sum); the ring variants differ in FFT round-off only.
+ * pfsh_level_autotune times every variant of the three stages at `batch`
+ * (one warm-up and `reps` launches each, HIP events on `stream`) on the
+ * level's internal workspace, and keeps the fastest for that batch's buckets.
+ * It synchronizes the stream, overwrites the level's workspace (which holds
+ * nothing between calls), and returns PFSH_EUNSUPPORTED while the stream is
+ * being captured; graphs captured earlier keep the variants they recorded.
+ * us_out (host, nullable) receives the microseconds per launch at
+ * [stage * PFSH_MAX_VARIANTS + variant].  One level must not be tuned and
+ * used on two streams at once.
+ * ------------------------------------------------------------------------- */
+#define PFSH_MAX_VARIANTS 8
+/* number of variants of a stage (0..2) on this level, or a negative status */
+int pfsh_variant_count(const pfsh_level* level, int stage);
+pfsh_status pfsh_level_set_variant(pfsh_level* level, int stage, int batch, int variant);
+pfsh_status pfsh_level_get_variant(const pfsh_level* level, int stage, int batch, int* variant);
+pfsh_status pfsh_level_autotune(pfsh_level* level, int batch, int reps, void* stream,
+                                float* us_out);
+
+/* ---------------------------------------------------------------------------
  * Two-level PFASST on one device (Sec. 5.2).  The n_ts time steps of a block
  * ("processors" P_0..P_{n_ts-1}) and `members` independent ensemble members
  * are one batch: slice index s = step * members + member, so a step's members

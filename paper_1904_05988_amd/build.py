@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfsh.so")
-SOURCES = ["tables.cpp", "level.cpp", "api.cpp", "pfasst.cpp",
+SOURCES = ["tables.cpp", "level.cpp", "api.cpp", "pfasst.cpp", "tune.cpp",
            "k_legendre.hip", "k_ring.hip", "k_spectral.hip"]
 ARCH = "gfx950"
 

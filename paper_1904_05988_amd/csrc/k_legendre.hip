@@ -59,10 +59,6 @@ __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void*
   }
 }
 
-template <class Op>
-struct Prefetch {
-  static constexpr int depth = Op::KIND == OP_BF16X3 ? 2 : 4;
-};
 
 // Block id -> (work item, column tile), XCD-aware: the hardware deals
 // consecutive block ids to the 8 XCDs in turn, so item i goes to XCD i % 8 and
@@ -93,7 +89,7 @@ __device__ __forceinline__ void store_run(R* dst, const R* v) {
 // waves then exchange their tiles through LDS so that every thread stores the
 // MC consecutive-m complex values of one (ring, field) as one contiguous run
 // (64 bytes) in the [slice][ring][field][parity][m] layout the ring stage reads.
-template <class Op, int MC>
+template <class Op, int MC, int PF>
 __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ tab,
                                                       const void* __restrict__ X,
                                                       typename Op::R* __restrict__ F4,
@@ -119,9 +115,9 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
     // small terms are summed before the large low-degree ones
     const MPInfo q = mpi[2 * m + p];
     const long long last = q.kbS - 1;
-    mma_loop<Op, Prefetch<Op>::depth>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
-                                      q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, r1, c1,
-                                      lane, acc[0], acc[1], acc[2], acc[3]);
+    mma_loop<Op, PF>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
+                     q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, r1, c1, lane, acc[0],
+                     acc[1], acc[2], acc[3]);
   }
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk) {
@@ -149,7 +145,11 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
   }
 }
 
-template <class Op>
+// Tile shapes: SHAPE 0 = 64 degrees x 64 columns (2x2 blocks per wave),
+// SHAPE 1 = 64 degrees x 32 columns with one row block per wave (1x2 blocks),
+// which keeps all four waves busy when there are only one or two column
+// blocks (small batches).
+template <class Op, int PF, int SHAPE>
 __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
                                                  const void* __restrict__ G,
                                                  typename Op::R* __restrict__ Y,
@@ -162,14 +162,13 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
   const WorkItem it = items[item];
   const MPInfo q = mpi[it.mp];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rb0 = it.tile * 4 + (wave >> 1) * 2;
-  const int cb0 = ct * 4 + (wave & 1) * 2;
+  const int rb0 = SHAPE == 0 ? it.tile * 4 + (wave >> 1) * 2 : it.tile * 4 + wave;
+  const int cb0 = SHAPE == 0 ? ct * 4 + (wave & 1) * 2 : ct * 2;
   if (rb0 >= q.rbA || cb0 >= CBn) return;
-  const bool r1 = rb0 + 1 < q.rbA, c1 = cb0 + 1 < CBn;
+  const bool r1 = SHAPE == 0 && rb0 + 1 < q.rbA, c1 = cb0 + 1 < CBn;
   typename Op::C acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-  mma_loop<Op, Prefetch<Op>::depth>(tab, G, q.tabA + rb0, (long long)q.rbA,
-                                    (long long)it.mp * kb2 * CBa + cb0, (long long)CBa, kb2, r1,
-                                    c1, lane, acc00, acc01, acc10, acc11);
+  mma_loop<Op, PF>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
+                   (long long)CBa, kb2, r1, c1, lane, acc00, acc01, acc10, acc11);
   const int base = ext_off(T, q.m);
   auto put = [&](const typename Op::C& acc, int rb, int cb) {
     const int c = cb * 16 + (lane & 15);
@@ -191,38 +190,77 @@ static inline unsigned xcd_grid(int nitems, int nct) {
   return (unsigned)(((nitems + 7) / 8) * 8 * nct);
 }
 
-template <class Op>
+template <class Op, int MC, int PF>
 static hipError_t synth_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2;
-  constexpr int MC = Op::KIND == OP_F64 ? 4 : 8;
-  hipLaunchKernelGGL((k_leg_synth<Op, MC>), dim3(xcd_grid(lv->nitemsS, nct)), dim3(64 * MC), 0, s,
-                     lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d, lv->itemsS, lv->nitemsS,
-                     nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J, lv->T, lv->Lp);
+  hipLaunchKernelGGL((k_leg_synth<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, nct)), dim3(64 * MC),
+                     0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d, lv->itemsS,
+                     lv->nitemsS, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J, lv->T, lv->Lp);
   return hipGetLastError();
 }
 
-template <class Op>
+template <class Op, int PF, int SHAPE>
 static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
-  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
-  hipLaunchKernelGGL(k_leg_anal<Op>, dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s, lv->tabA,
-                     lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA, nct,
-                     lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
+  const int CBn = (ncols + 15) / 16, nct = SHAPE == 0 ? (CBn + 3) / 4 : (CBn + 1) / 2;
+  hipLaunchKernelGGL((k_leg_anal<Op, PF, SHAPE>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s,
+                     lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
+                     nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
   return hipGetLastError();
+}
+
+// Variant lists (index 0 = default):
+//   synthesis, prefetch depth of the K loop: FP64 / FP32 4 2 8; BF16x3 2 4
+//   analysis, (prefetch depth, tile shape): FP64 / FP32 (4,0) (2,0) (8,0) (4,1)
+//     (8,1); BF16x3 (2,0) (4,0) (2,1) (4,1)
+// Neither changes the order of any sum, so all variants give the same bits.
+int leg_variant_count(int op, int stage) {
+  if (stage == TS_SYNTH) return op == OP_BF16X3 ? 2 : 3;
+  return op == OP_BF16X3 ? 4 : 5;
 }
 
 hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
+  const int v = lv->variant[TS_SYNTH][tune_bucket((ncols + 15) / 16)];
   switch (lv->op) {
-    case OP_F64: return synth_impl<OpF64>(lv, ncols, nf, s);
-    case OP_F32: return synth_impl<OpF32>(lv, ncols, nf, s);
-    default: return synth_impl<OpBF3>(lv, ncols, nf, s);
+    case OP_F64:
+      return v == 1 ? synth_impl<OpF64, 4, 2>(lv, ncols, nf, s)
+           : v == 2 ? synth_impl<OpF64, 4, 8>(lv, ncols, nf, s)
+                    : synth_impl<OpF64, 4, 4>(lv, ncols, nf, s);
+    case OP_F32:
+      return v == 1 ? synth_impl<OpF32, 8, 2>(lv, ncols, nf, s)
+           : v == 2 ? synth_impl<OpF32, 8, 8>(lv, ncols, nf, s)
+                    : synth_impl<OpF32, 8, 4>(lv, ncols, nf, s);
+    default:
+      return v == 1 ? synth_impl<OpBF3, 8, 4>(lv, ncols, nf, s)
+                    : synth_impl<OpBF3, 8, 2>(lv, ncols, nf, s);
+  }
+}
+
+template <class Op>
+static hipError_t anal_variant(const pfsh_level* lv, int v, int ncols, hipStream_t s) {
+  if constexpr (Op::KIND == OP_BF16X3) {
+    switch (v) {
+      case 1: return anal_impl<Op, 4, 0>(lv, ncols, s);
+      case 2: return anal_impl<Op, 2, 1>(lv, ncols, s);
+      case 3: return anal_impl<Op, 4, 1>(lv, ncols, s);
+      default: return anal_impl<Op, 2, 0>(lv, ncols, s);
+    }
+  } else {
+    switch (v) {
+      case 1: return anal_impl<Op, 2, 0>(lv, ncols, s);
+      case 2: return anal_impl<Op, 8, 0>(lv, ncols, s);
+      case 3: return anal_impl<Op, 4, 1>(lv, ncols, s);
+      case 4: return anal_impl<Op, 8, 1>(lv, ncols, s);
+      default: return anal_impl<Op, 4, 0>(lv, ncols, s);
+    }
   }
 }
 
 hipError_t launch_leg_anal(const pfsh_level* lv, int ncols, int /*nf*/, hipStream_t s) {
+  const int v = lv->variant[TS_ANAL][tune_bucket((ncols + 15) / 16)];
   switch (lv->op) {
-    case OP_F64: return anal_impl<OpF64>(lv, ncols, s);
-    case OP_F32: return anal_impl<OpF32>(lv, ncols, s);
-    default: return anal_impl<OpBF3>(lv, ncols, s);
+    case OP_F64: return anal_variant<OpF64>(lv, v, ncols, s);
+    case OP_F32: return anal_variant<OpF32>(lv, v, ncols, s);
+    default: return anal_variant<OpBF3>(lv, v, ncols, s);
   }
 }
 

@@ -38,19 +38,20 @@ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
 __host__ __device__ constexpr int padded(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
 
-// radix of stage s for a length-N transform: 16s first, then 8, 4, 2, then a 3
-__host__ __device__ constexpr int radix_of(int N, int s) {
+// radix of stage s for a length-N transform with radices up to CAP (16, 8 or
+// 4): the largest first, then 8, 4, 2, then a 3
+__host__ __device__ constexpr int radix_of(int N, int s, int CAP = 16) {
   int n = N, st = 0;
-  while (n % 16 == 0) { if (st == s) return 16; n /= 16; ++st; }
-  while (n % 8 == 0) { if (st == s) return 8; n /= 8; ++st; }
+  while (CAP >= 16 && n % 16 == 0) { if (st == s) return 16; n /= 16; ++st; }
+  while (CAP >= 8 && n % 8 == 0) { if (st == s) return 8; n /= 8; ++st; }
   while (n % 4 == 0) { if (st == s) return 4; n /= 4; ++st; }
   while (n % 2 == 0) { if (st == s) return 2; n /= 2; ++st; }
   while (n % 3 == 0) { if (st == s) return 3; n /= 3; ++st; }
   return 0;
 }
-__host__ __device__ constexpr int nstages(int N) {
+__host__ __device__ constexpr int nstages(int N, int CAP = 16) {
   int s = 0;
-  while (radix_of(N, s) != 0) ++s;
+  while (radix_of(N, s, CAP) != 0) ++s;
   return s;
 }
 
@@ -172,12 +173,12 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   __syncthreads();
 }
 
-template <typename R, int N, int NSIG, int NT, int SIGN, int S = 0, int NS = 1>
+template <typename R, int N, int NSIG, int NT, int SIGN, int CAP = 16, int S = 0, int NS = 1>
 __device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
-  if constexpr (S < nstages(N)) {
-    constexpr int RAD = radix_of(N, S);
+  if constexpr (S < nstages(N, CAP)) {
+    constexpr int RAD = radix_of(N, S, CAP);
     fft_stage<R, N, RAD, NSIG, NT, SIGN, NS>(buf, tw);
-    fft_run<R, N, NSIG, NT, SIGN, S + 1, NS * RAD>(buf, tw);
+    fft_run<R, N, NSIG, NT, SIGN, CAP, S + 1, NS * RAD>(buf, tw);
   }
 }
 
@@ -234,7 +235,7 @@ __device__ __forceinline__ void split_pair(const cpx<R>* sig, int N, int m, cpx<
   ys = {(R)0.5 * (z.y + w.y), (R)0.5 * (w.x - z.x)};
 }
 
-template <class Op, int N>
+template <class Op, int N, int CAP>
 __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restrict__ F4,
                                                  void* __restrict__ G,
                                                  const double* __restrict__ mu,
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
     load_pair<R>(buf + f * SP, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
   }
   __syncthreads();
-  fft_run<R, N, 4, NT, +1>(buf, tw);
+  fft_run<R, N, 4, NT, +1, CAP>(buf, tw);
   const double muj = mu[j];
   const R fn = (R)(two_omega * muj), fs = -fn;
   for (int k = tid; k < N; k += NT) {
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
     buf[4 * SP + pk] = {(R)0.5 * (u.x * u.x + v.x * v.x), (R)0.5 * (u.y * u.y + v.y * v.y)};
   }
   __syncthreads();
-  fft_run<R, N, 5, NT, -1>(buf, tw);
+  fft_run<R, N, 5, NT, -1, CAP>(buf, tw);
   const R scale = (R)(wq[j] / ((1.0 - muj * muj) * (double)N));
   for (int i = tid; i < 5 * L; i += NT) {
     const int m = i / 5, f = i - m * 5;
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ gr
 }
 
 // ---------------------------------------------------------------- dispatch
-template <class Op, int N>
+template <class Op, int N, int CAP>
 static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const double* gin,
                               double* gout, hipStream_t s) {
   typedef typename Op::R R;
@@ -373,9 +374,9 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
   if (kind == 0) {
     shm = (size_t)5 * padded_len(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
-      (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N>,
+      (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ring_rhs<Op, N>), dim3(lv->J, count), dim3(256), shm, s,
+    hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP>), dim3(lv->J, count), dim3(256), shm, s,
                        (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->Lp, lv->kb2,
                        lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
@@ -396,24 +397,37 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
   return hipGetLastError();
 }
 
+// Ring-stage variants (index 0 = default): the largest FFT radix, 16, 8 or 4
+// (RHS kernel only; the scalar transforms use 16).
+int ring_variant_count() { return 3; }
+
+template <class Op, int N>
+static hipError_t ring_cap(int kind, const pfsh_level* lv, int count, const double* gin,
+                           double* gout, hipStream_t s) {
+  const int v = kind == 0 ? lv->variant[TS_RING][tune_bucket(count)] : 0;
+  if (v == 1) return ring_launch<Op, N, 8>(kind, lv, count, gin, gout, s);
+  if (v == 2) return ring_launch<Op, N, 4>(kind, lv, count, gin, gout, s);
+  return ring_launch<Op, N, 16>(kind, lv, count, gin, gout, s);
+}
+
 template <class Op>
 static hipError_t ring_by_n(int kind, const pfsh_level* lv, int count, const double* gin,
                             double* gout, hipStream_t s) {
   switch (lv->nlon) {
-    case 16: return ring_launch<Op, 16>(kind, lv, count, gin, gout, s);
-    case 24: return ring_launch<Op, 24>(kind, lv, count, gin, gout, s);
-    case 32: return ring_launch<Op, 32>(kind, lv, count, gin, gout, s);
-    case 48: return ring_launch<Op, 48>(kind, lv, count, gin, gout, s);
-    case 64: return ring_launch<Op, 64>(kind, lv, count, gin, gout, s);
-    case 96: return ring_launch<Op, 96>(kind, lv, count, gin, gout, s);
-    case 128: return ring_launch<Op, 128>(kind, lv, count, gin, gout, s);
-    case 192: return ring_launch<Op, 192>(kind, lv, count, gin, gout, s);
-    case 256: return ring_launch<Op, 256>(kind, lv, count, gin, gout, s);
-    case 384: return ring_launch<Op, 384>(kind, lv, count, gin, gout, s);
-    case 512: return ring_launch<Op, 512>(kind, lv, count, gin, gout, s);
-    case 768: return ring_launch<Op, 768>(kind, lv, count, gin, gout, s);
-    case 1024: return ring_launch<Op, 1024>(kind, lv, count, gin, gout, s);
-    case 1536: return ring_launch<Op, 1536>(kind, lv, count, gin, gout, s);
+    case 16: return ring_cap<Op, 16>(kind, lv, count, gin, gout, s);
+    case 24: return ring_cap<Op, 24>(kind, lv, count, gin, gout, s);
+    case 32: return ring_cap<Op, 32>(kind, lv, count, gin, gout, s);
+    case 48: return ring_cap<Op, 48>(kind, lv, count, gin, gout, s);
+    case 64: return ring_cap<Op, 64>(kind, lv, count, gin, gout, s);
+    case 96: return ring_cap<Op, 96>(kind, lv, count, gin, gout, s);
+    case 128: return ring_cap<Op, 128>(kind, lv, count, gin, gout, s);
+    case 192: return ring_cap<Op, 192>(kind, lv, count, gin, gout, s);
+    case 256: return ring_cap<Op, 256>(kind, lv, count, gin, gout, s);
+    case 384: return ring_cap<Op, 384>(kind, lv, count, gin, gout, s);
+    case 512: return ring_cap<Op, 512>(kind, lv, count, gin, gout, s);
+    case 768: return ring_cap<Op, 768>(kind, lv, count, gin, gout, s);
+    case 1024: return ring_cap<Op, 1024>(kind, lv, count, gin, gout, s);
+    case 1536: return ring_cap<Op, 1536>(kind, lv, count, gin, gout, s);
   }
   return hipErrorInvalidValue;
 }

@@ -57,6 +57,21 @@ struct WorkItem {      // one workgroup tile of a Legendre contraction
 // of one ring are contiguous, so each lane pair writes 64 bytes at once.
 __host__ __device__ inline int synth_mc(int op) { return op == OP_F64 ? 4 : 8; }
 
+// Kernel variants chosen per level and per size bucket (pfsh_level_autotune):
+// the Legendre synthesis (orders per workgroup, prefetch depth), the Legendre
+// analysis (prefetch depth) and the ring stage (largest FFT radix).  Variant 0
+// is the built-in default.  Bucket b holds sizes in (2^(b-1), 2^b]; the size is
+// the number of 16-column blocks for the Legendre stages and the batch for
+// the ring stage.
+enum TuneStage { TS_SYNTH = 0, TS_ANAL = 1, TS_RING = 2, TS_COUNT = 3 };
+constexpr int kTuneBuckets = 13;
+inline int tune_bucket(int n) {
+  int b = 0;
+  while (b < kTuneBuckets - 1 && (1 << b) < n) ++b;
+  return b;
+}
+int variant_count(int op, int stage);
+
 }  // namespace pfsh
 
 struct pfsh_level {
@@ -90,6 +105,7 @@ struct pfsh_level {
   double* red = nullptr;   // residual partial maxima
   size_t red_len = 0;
   size_t bytes_tables = 0, bytes_work = 0;
+  unsigned char variant[pfsh::TS_COUNT][pfsh::kTuneBuckets] = {};   // chosen kernel variants
   // diagnostic kernel timing (pfsh_profile_*)
   mutable bool prof_on = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[PFSH_K_COUNT];

@@ -1,0 +1,111 @@
+// Autotuner of the transform kernels.  Every level keeps, per size bucket, the
+// variant it launches for the Legendre synthesis, the ring stage and the
+// Legendre analysis (pfsh_internal.h lists the variants).  pfsh_level_autotune
+// times each variant on the level's own workspace at the given batch and keeps
+// the fastest; pfsh_level_set_variant pins one by hand.
+#include "pfsh_internal.h"
+
+namespace pfsh {
+int leg_variant_count(int op, int stage);
+int ring_variant_count();
+
+int variant_count(int op, int stage) {
+  return stage == TS_RING ? ring_variant_count() : leg_variant_count(op, stage);
+}
+}  // namespace pfsh
+
+using namespace pfsh;
+
+namespace {
+
+// the bucket that an RHS evaluation of `batch` states uses in each stage
+int stage_bucket(int stage, int batch) {
+  if (stage == TS_SYNTH) return tune_bucket((2 * 4 * batch + 15) / 16);
+  if (stage == TS_ANAL) return tune_bucket((2 * 5 * batch + 15) / 16);
+  return tune_bucket(batch);
+}
+
+hipError_t launch_stage(const pfsh_level* lv, int stage, int batch, hipStream_t s) {
+  if (stage == TS_SYNTH) return launch_leg_synth(lv, 2 * 4 * batch, 4, s);
+  if (stage == TS_RING) return launch_ring_rhs(lv, batch, s);
+  return launch_leg_anal(lv, 2 * 5 * batch, 5, s);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+extern "C" int pfsh_variant_count(const pfsh_level* lv, int stage) {
+  if (!lv || stage < 0 || stage >= TS_COUNT) return PFSH_EINVAL;
+  return variant_count(lv->op, stage);
+}
+
+extern "C" pfsh_status pfsh_level_set_variant(pfsh_level* lv, int stage, int batch, int variant) {
+  if (!lv || stage < 0 || stage >= TS_COUNT) return PFSH_EINVAL;
+  if (batch < 1 || batch > lv->d.max_batch) return PFSH_ESHAPE;
+  if (variant < 0 || variant >= variant_count(lv->op, stage)) return PFSH_EINVAL;
+  lv->variant[stage][stage_bucket(stage, batch)] = (unsigned char)variant;
+  return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_level_get_variant(const pfsh_level* lv, int stage, int batch,
+                                              int* variant) {
+  if (!lv || !variant || stage < 0 || stage >= TS_COUNT) return PFSH_EINVAL;
+  if (batch < 1 || batch > lv->d.max_batch) return PFSH_ESHAPE;
+  *variant = lv->variant[stage][stage_bucket(stage, batch)];
+  return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_level_autotune(pfsh_level* lv, int batch, int reps, void* stream,
+                                           float* us_out) {
+  if (!lv || reps < 1 || reps > 1000) return PFSH_EINVAL;
+  if (batch < 1 || batch > lv->d.max_batch) return PFSH_ESHAPE;
+  DeviceGuard g(lv->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return PFSH_EHIP;
+  if (cap != hipStreamCaptureStatusNone) return PFSH_EUNSUPPORTED;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return PFSH_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return PFSH_EHIP;
+  }
+  hipError_t err = hipSuccess;
+  for (int stage = 0; stage < TS_COUNT && err == hipSuccess; ++stage) {
+    unsigned char& slot = lv->variant[stage][stage_bucket(stage, batch)];
+    const unsigned char keep = slot;
+    const int nv = variant_count(lv->op, stage);
+    int best = keep;
+    float best_us = 0.0f;
+    for (int v = 0; v < nv && err == hipSuccess; ++v) {
+      slot = (unsigned char)v;
+      err = launch_stage(lv, stage, batch, s);                    // warm-up
+      if (err == hipSuccess) err = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_stage(lv, stage, batch, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      const float us = 1e3f * ms / (float)reps;
+      if (us_out) us_out[stage * PFSH_MAX_VARIANTS + v] = us;
+      if (err == hipSuccess && (v == 0 || us < best_us)) {
+        best = v;
+        best_us = us;
+      }
+    }
+    slot = (unsigned char)(err == hipSuccess ? best : keep);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return err == hipSuccess ? PFSH_OK : PFSH_EHIP;
+}

@@ -55,6 +55,10 @@ _SIGS = {
     "pfsh_fas_tau": ([_P, _P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_profile_enable": ([_P, _I], _I),
     "pfsh_profile_read": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
+    "pfsh_variant_count": ([_P, _I], _I),
+    "pfsh_level_set_variant": ([_P, _I, _I, _I], _I),
+    "pfsh_level_get_variant": ([_P, _I, _I, ctypes.POINTER(_I)], _I),
+    "pfsh_level_autotune": ([_P, _I, _I, _P, _P], _I),
     "pfsh_pfasst_create": ([_P, _P, _I, _I, ctypes.POINTER(_P)], _I),
     "pfsh_pfasst_destroy": ([_P], None),
     "pfsh_pfasst_predict": ([_P, _D, _P, _P, _P, _P, _P], _I),
@@ -170,6 +174,40 @@ class Level:
         _check(lib().pfsh_profile_read(self._h, self.KERNELS[kernel], ctypes.byref(n),
                                        ctypes.byref(ms)), "pfsh_profile_read")
         return n.value, ms.value
+
+    # -- transform-kernel variants and the autotuner
+    STAGES = {"synth": 0, "anal": 1, "ring": 2}
+    MAX_VARIANTS = 8
+
+    def variant_count(self, stage):
+        n = lib().pfsh_variant_count(self._h, self.STAGES[stage])
+        if n < 0:
+            _check(n, "pfsh_variant_count")
+        return n
+
+    def set_variant(self, stage, batch, variant):
+        _check(lib().pfsh_level_set_variant(self._h, self.STAGES[stage], int(batch), int(variant)),
+               "pfsh_level_set_variant")
+
+    def get_variant(self, stage, batch):
+        v = ctypes.c_int()
+        _check(lib().pfsh_level_get_variant(self._h, self.STAGES[stage], int(batch),
+                                            ctypes.byref(v)), "pfsh_level_get_variant")
+        return v.value
+
+    def autotune(self, batch, reps=20):
+        """Time every transform-kernel variant at `batch` on the current stream
+        and keep the fastest; returns {stage: (chosen, [us per variant])}."""
+        us = (ctypes.c_float * (3 * self.MAX_VARIANTS))()
+        s = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(lib().pfsh_level_autotune(self._h, int(batch), int(reps), s, us),
+               "pfsh_level_autotune")
+        out = {}
+        for name, st in self.STAGES.items():
+            n = self.variant_count(name)
+            out[name] = (self.get_variant(name, batch),
+                         [us[st * self.MAX_VARIANTS + v] for v in range(n)])
+        return out
 
     # -- allocation helpers (caller-owned device memory)
     def state(self, batch):

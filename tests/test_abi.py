@@ -89,6 +89,11 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.pfsh_pfasst_iterate(None, 1.0, one, one, one, 0, None) == -1
     assert L.pfsh_check_finite(None, 3, None) == -1
     assert L.pfsh_check_finite(one, 0, None) == 0
+    v = ctypes.c_int()
+    assert L.pfsh_variant_count(None, 0) == -1
+    assert L.pfsh_level_set_variant(None, 0, 1, 0) == -1
+    assert L.pfsh_level_get_variant(None, 0, 1, ctypes.byref(v)) == -1
+    assert L.pfsh_level_autotune(None, 1, 5, None, None) == -1
     L.pfsh_level_destroy(None)
     L.pfsh_pfasst_destroy(None)
 

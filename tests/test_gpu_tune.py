@@ -1,0 +1,66 @@
+"""Transform-kernel variants and the autotuner: every Legendre variant gives
+the default's bits, every ring variant (a different FFT factorization) stays
+within round-off of the oracle, and the tuner keeps a valid choice without
+changing results beyond that."""
+
+import numpy as np
+import pytest
+
+from oracle import swe
+from paper_1904_05988_amd import pfsh
+from tests._gpu import level_pair, rel_err, seeded, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "fp32", "bf16x3"]
+
+
+def _rhs(gl, x):
+    fe, _ = gl.rhs(x)
+    return to_host(fe)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 3), (63, 96, 192, 13)])
+def test_legendre_variants_are_bitwise_equal(prec, T, nlat, nlon, B):
+    gl = pfsh.Level(T, nlat, nlon, 3, max_batch=B, precision=prec)
+    x = to_dev(seeded(T, range(B)))
+    base = _rhs(gl, x)
+    for stage in ("synth", "anal"):
+        for v in range(1, gl.variant_count(stage)):
+            gl.set_variant(stage, B, v)
+            assert gl.get_variant(stage, B) == v
+            assert np.array_equal(_rhs(gl, x), base), (stage, v)
+        gl.set_variant(stage, B, 0)
+
+
+@pytest.mark.parametrize("T,nlat,nlon", [(31, 48, 96), (127, 192, 384)])
+def test_ring_variants_match_oracle(T, nlat, nlon):
+    gl, ol = level_pair(T, nlat, nlon, 3, max_batch=2)
+    states = seeded(T, (7, 8))
+    ref = [swe.explicit_rhs(ol, s) for s in states]
+    for v in range(gl.variant_count("ring")):
+        gl.set_variant("ring", 2, v)
+        fe = _rhs(gl, to_dev(states))
+        for b in range(2):
+            assert np.all(rel_err(fe[b], ref[b]) <= 1e-12), (v, b, rel_err(fe[b], ref[b]))
+
+
+def test_autotune_keeps_a_valid_choice_and_results():
+    T, nlat, nlon, B = 63, 96, 192, 4
+    gl, ol = level_pair(T, nlat, nlon, 3, max_batch=B)
+    states = seeded(T, range(20, 20 + B))
+    for batch in (1, B):
+        out = gl.autotune(batch, reps=3)
+        for stage, (chosen, us) in out.items():
+            assert len(us) == gl.variant_count(stage)
+            assert 0 <= chosen < len(us)
+            assert all(t > 0 for t in us), (stage, us)
+            assert us[chosen] == min(us)
+    fe = _rhs(gl, to_dev(states))
+    for b in range(B):
+        assert np.all(rel_err(fe[b], swe.explicit_rhs(ol, states[b])) <= 1e-12)
+    with pytest.raises(pfsh.PfshError):
+        gl.set_variant("anal", B + 1, 0)
+    with pytest.raises(pfsh.PfshError):
+        gl.set_variant("synth", 1, 99)
