@@ -187,10 +187,14 @@ typedef enum {
   PFSH_K_LEG_SYNTH = 0,   /* Legendre synthesis contraction (MFMA)        */
   PFSH_K_RING = 1,        /* ring FFTs + grid products                     */
   PFSH_K_LEG_ANAL = 2,    /* Legendre analysis contraction (MFMA)          */
-  PFSH_K_ASSEMBLE = 3,    /* spectral assembly of F_E                      */
-  PFSH_K_PREP = 4,        /* transform input preparation                   */
-  PFSH_K_SWEEP_NODE = 5,  /* per-node SDC update and implicit solve        */
-  PFSH_K_SWEEP_PRE = 6,   /* per-sweep SDC accumulation of old terms       */
+  PFSH_K_ASSEMBLE = 3,    /* spectral assembly of F_E (RHS calls, last
+                             node of a sweep)                              */
+  PFSH_K_PREP = 4,        /* transform input preparation (RHS calls)       */
+  PFSH_K_SWEEP_NODE = 5,  /* sweep node: F_E assembly of the previous node,
+                             old-iterate terms (node 1), update, implicit
+                             solve, F_I, transform input of the new state  */
+  PFSH_K_SWEEP_PRE = 6,   /* not launched: the old-iterate terms run in the
+                             first node kernel (kept for numbering)        */
   PFSH_K_COUNT = 7
 } pfsh_kernel_id;
 pfsh_status pfsh_profile_enable(pfsh_level* level, int on);

@@ -33,15 +33,10 @@ inline pfsh_status st_of(hipError_t e) { return e == hipSuccess ? PFSH_OK : PFSH
 
 namespace pfsh {
 
-// F_E (and optionally F_I) at `batch` states spaced `sstride` complex values
-// apart; outputs spaced fes / fis apart.
-hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
-                       long long fes, double* fi, long long fis, int batch, hipStream_t s) {
-  {
-    ProfScope p(lv, PFSH_K_PREP, s);
-    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
-  }
-  if (!fe) return hipSuccess;
+// Legendre synthesis, ring stage and Legendre analysis of the operand that the
+// preceding kernel wrote (batch states); the products end in the analysis
+// workspace Y.
+static hipError_t transforms(const pfsh_level* lv, int batch, hipStream_t s) {
   {
     ProfScope p(lv, PFSH_K_LEG_SYNTH, s);
     PFSH_TRY(launch_leg_synth(lv, 2 * 4 * batch, 4, s));
@@ -50,31 +45,55 @@ hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstr
     ProfScope p(lv, PFSH_K_RING, s);
     PFSH_TRY(launch_ring_rhs(lv, batch, s));
   }
+  ProfScope p(lv, PFSH_K_LEG_ANAL, s);
+  return launch_leg_anal(lv, 2 * 5 * batch, 5, s);
+}
+
+// F_I of `batch` states spaced `sstride` complex values apart (when fi is not
+// null) and the transforms of F_E up to the analysis; F_E itself is assembled
+// by the next sweep's first node kernel.
+hipError_t rhs_pending(const pfsh_level* lv, const double* state, long long sstride, double* fi,
+                       long long fis, int batch, hipStream_t s) {
   {
-    ProfScope p(lv, PFSH_K_LEG_ANAL, s);
-    PFSH_TRY(launch_leg_anal(lv, 2 * 5 * batch, 5, s));
+    ProfScope p(lv, PFSH_K_PREP, s);
+    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
   }
+  return transforms(lv, batch, s);
+}
+
+// F_E (and optionally F_I) at `batch` states spaced `sstride` complex values
+// apart; outputs spaced fes / fis apart.
+hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
+                       long long fes, double* fi, long long fis, int batch, hipStream_t s) {
+  if (!fe) {
+    ProfScope p(lv, PFSH_K_PREP, s);
+    return launch_prep_rhs(lv, state, sstride, fi, fis, batch, s);
+  }
+  PFSH_TRY(rhs_pending(lv, state, sstride, fi, fis, batch, s));
   ProfScope p(lv, PFSH_K_ASSEMBLE, s);
   return launch_assemble(lv, fe, fes, batch, s);
 }
 
-// one sweep on [batch][nn][3][K] arrays (validated by the caller)
+// One sweep on [batch][nn][3][K] arrays (validated by the caller): per node the
+// fused node kernel (update, implicit solve, F_I, synthesis input; on node 1
+// also the old-iterate terms) and the transforms of the new state; the F_E
+// assembly of each node runs in the next node's kernel, the last one on its
+// own.  node0_pending: F_E at node 0 is still in the analysis workspace
+// (rhs_pending ran on the node-0 state) and node 1's kernel assembles it.
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s) {
+                      const double* tau, int batch, hipStream_t s, bool node0_pending) {
   const long long n3k = 3LL * lv->K;
   const long long stride = lv->nn * n3k;
-  {
-    ProfScope p(lv, PFSH_K_SWEEP_PRE, s);
-    PFSH_TRY(launch_sweep_pre(lv, dt, th, fe, fi, tau, batch, s));
-  }
   for (int i = 1; i <= lv->M; ++i) {
+    const int asm_node = i > 1 ? i - 1 : (node0_pending ? 0 : -1);
     {
       ProfScope p(lv, PFSH_K_SWEEP_NODE, s);
-      PFSH_TRY(launch_sweep_node(lv, i, dt, th, fe, fi, batch, s));
+      PFSH_TRY(launch_sweep_step(lv, i, asm_node, dt, th, fe, fi, tau, batch, s));
     }
-    PFSH_TRY(rhs_strided(lv, th + 2 * i * n3k, stride, fe + 2 * i * n3k, stride, nullptr, 0, batch, s));
+    PFSH_TRY(transforms(lv, batch, s));
   }
-  return hipSuccess;
+  ProfScope p(lv, PFSH_K_ASSEMBLE, s);
+  return launch_assemble(lv, fe + 2 * lv->M * n3k, stride, batch, s);
 }
 
 }  // namespace pfsh

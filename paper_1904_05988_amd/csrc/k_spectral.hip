@@ -37,14 +37,80 @@ struct Phys {
 };
 
 // -------------------------------------------------------------- RHS prep
-// One workgroup per (m, batch entry).  Writes the synthesis data operand for
-// the four fields Phi', zeta, U, V at degrees n' = m..T+1:
+// Synthesis data operand of the four fields Phi', zeta, U, V at degree
+// n' = m..T+1 of order m (Sec. 2-3):
 //   Phi'_n' = Phi_n' (minus sqrt(2) Phibar at (0,0)), zeta_n'      (0 at n' = T+1)
 //   U_n' = (1/a) [ i m chi_n' - psit_n' ],  V_n' = (1/a) [ i m psi_n' + chit_n' ]
 //   psit_n' = -(n'-1) eps_n' psi_{n'-1} + (n'+2) eps_{n'+1} psi_{n'+1}
-// (the H_n^m = (1-mu^2) dP_n^m/dmu terms rewritten on P_{n'}, Sec. 2-3), with
+// (the H_n^m = (1-mu^2) dP_n^m/dmu terms rewritten on P_{n'}), with
 // psi = -a^2 zeta/(n(n+1)), chi = -a^2 delta/(n(n+1)) (Helmholtz, Sec. 2).
-// Optionally F_I = L(Theta) per mode.
+// `get(v, nn)` returns variable v (0 Phi, 1 zeta, 2 delta) at degree nn of
+// order m, for m <= nn <= T.
+template <class Get>
+__device__ __forceinline__ void prep_fields(Get get, int m, int n, int T, Phys ph, C2 out[4]) {
+  const double ia = 1.0 / ph.a, a2 = ph.a * ph.a;
+  auto inv_lap = [&](int v, int nn) -> C2 {
+    if (nn < m || nn > T || nn == 0) return {0.0, 0.0};
+    const C2 z = get(v, nn);
+    const double sc = -a2 / ((double)nn * (nn + 1));
+    return {sc * z.x, sc * z.y};
+  };
+  C2 phi = {0, 0}, zeta = {0, 0};
+  if (n <= T) {
+    phi = get(0, n);
+    zeta = get(1, n);
+  }
+  if (n == 0) phi.x -= 1.4142135623730950488 * ph.phibar;
+  const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
+  const C2 ps_m = inv_lap(1, n - 1), ps_p = inv_lap(1, n + 1), ps_0 = inv_lap(1, n);
+  const C2 ch_m = inv_lap(2, n - 1), ch_p = inv_lap(2, n + 1), ch_0 = inv_lap(2, n);
+  const double cm = -(double)(n - 1) * e0, cp = (double)(n + 2) * e1;
+  const C2 pst = {cm * ps_m.x + cp * ps_p.x, cm * ps_m.y + cp * ps_p.y};
+  const C2 cht = {cm * ch_m.x + cp * ch_p.x, cm * ch_m.y + cp * ch_p.y};
+  // i m chi = (-m chi.y, m chi.x)
+  out[0] = phi;
+  out[1] = zeta;
+  out[2] = {ia * (-m * ch_0.y - pst.x), ia * (m * ch_0.x - pst.y)};
+  out[3] = {ia * (-m * ps_0.y + cht.x), ia * (m * ps_0.x + cht.y)};
+}
+
+// Store the 16 columns (2 slices x 4 fields x re/im) of degree n of order m
+// into the synthesis data operand.
+template <class Op>
+__device__ __forceinline__ void store_operand(void* X, const MPInfo* __restrict__ mpi, int m, int n,
+                                              int CBs, int b0, const typename Op::R* vals) {
+  typedef typename Op::R R;
+  const int p = (n - m) & 1, i = (n - m) >> 1;
+  const MPInfo q = mpi[2 * m + p];
+  const int KB = Op::KB;
+  const long long blk = q.xS + (long long)(i / KB) * CBs + (b0 * 8) / 16;
+  const int kk = i % KB;
+  if constexpr (Op::KIND == OP_BF16X3) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Op::store(X, blk, (kk >> 3) * 16 + c, kk & 7, vals[c]);
+  } else {
+    R* dst = reinterpret_cast<R*>(X) + blk * 64 + kk * 16;   // 16 consecutive lanes
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+      for (int c = 0; c < 16; c += 4)
+        *reinterpret_cast<float4*>(dst + c) = make_float4(vals[c], vals[c + 1], vals[c + 2], vals[c + 3]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 16; c += 2)
+        *reinterpret_cast<double2*>(dst + c) = make_double2(vals[c], vals[c + 1]);
+    }
+  }
+}
+
+// F_I = L(Theta) of one mode (Sec. 2): lam = -n(n+1)/a^2.
+__device__ __forceinline__ void linear_mode(double lam, Phys ph, C2 p, C2 z, C2 d, C2 out[3]) {
+  out[0] = {-ph.phibar * d.x + ph.nu * lam * p.x, -ph.phibar * d.y + ph.nu * lam * p.y};
+  out[1] = {ph.nu * lam * z.x, ph.nu * lam * z.y};
+  out[2] = {-lam * p.x + ph.nu * lam * d.x, -lam * p.y + ph.nu * lam * d.y};
+}
+
+// One workgroup per (m, pair of slices): the synthesis operand of the states
+// (and optionally F_I = L(Theta) per mode).
 template <class Op>
 __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th, long long sstride,
                                                  double* __restrict__ fi, long long fstride,
@@ -54,75 +120,31 @@ __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th,
   const int m = blockIdx.x, b0 = 2 * blockIdx.y;   // two slices per workgroup: 16 columns
   const int K = (T + 1) * (T + 2) / 2;
   const int off = spec_off(T, m);
-  const double ia = 1.0 / ph.a, a2 = ph.a * ph.a;
   for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
     R vals[16];
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       const int b = b0 + bb;
-      C2 phi = {0, 0}, zeta = {0, 0}, U = {0, 0}, V = {0, 0};
+      C2 v4[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
       if (b < batch) {
         const double* P = th + (size_t)b * sstride * 2;
-        const double* Pzeta = P + 2 * K;
-        const double* Pdelta = P + 4 * K;
-        auto psi = [&](const double* base, int nn) -> C2 {   // inverse Laplacian at (m, nn)
-          if (nn < m || nn > T || nn == 0) return {0.0, 0.0};
-          C2 z = ld2(base + 2 * (off + nn - m));
-          const double sc = -a2 / ((double)nn * (nn + 1));
-          return {sc * z.x, sc * z.y};
-        };
-        if (n <= T) {
-          phi = ld2(P + 2 * (off + n - m));
-          zeta = ld2(Pzeta + 2 * (off + n - m));
-          if (fi) {
-            const C2 dl = ld2(Pdelta + 2 * (off + n - m));
-            const double lam = -(double)n * (n + 1) / a2;
-            double* F = fi + (size_t)b * fstride * 2;
-            st2(F + 2 * (off + n - m), {-ph.phibar * dl.x + ph.nu * lam * phi.x,
-                                        -ph.phibar * dl.y + ph.nu * lam * phi.y});
-            st2(F + 2 * (K + off + n - m), {ph.nu * lam * zeta.x, ph.nu * lam * zeta.y});
-            st2(F + 2 * (2 * K + off + n - m), {-lam * phi.x + ph.nu * lam * dl.x,
-                                                -lam * phi.y + ph.nu * lam * dl.y});
-          }
+        auto get = [&](int v, int nn) { return ld2(P + 2 * ((size_t)v * K + off + nn - m)); };
+        if (fi && n <= T) {
+          const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
+          C2 f[3];
+          linear_mode(lam, ph, get(0, n), get(1, n), get(2, n), f);
+          double* F = fi + (size_t)b * fstride * 2;
+          for (int v = 0; v < 3; ++v) st2(F + 2 * ((size_t)v * K + off + n - m), f[v]);
         }
-        if (n == 0) phi.x -= 1.4142135623730950488 * ph.phibar;
-        const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
-        const C2 ps_m = psi(Pzeta, n - 1), ps_p = psi(Pzeta, n + 1), ps_0 = psi(Pzeta, n);
-        const C2 ch_m = psi(Pdelta, n - 1), ch_p = psi(Pdelta, n + 1), ch_0 = psi(Pdelta, n);
-        const double cm = -(double)(n - 1) * e0, cp = (double)(n + 2) * e1;
-        const C2 pst = {cm * ps_m.x + cp * ps_p.x, cm * ps_m.y + cp * ps_p.y};
-        const C2 cht = {cm * ch_m.x + cp * ch_p.x, cm * ch_m.y + cp * ch_p.y};
-        // i m chi = (-m chi.y, m chi.x)
-        U = {ia * (-m * ch_0.y - pst.x), ia * (m * ch_0.x - pst.y)};
-        V = {ia * (-m * ps_0.y + cht.x), ia * (m * ps_0.x + cht.y)};
+        prep_fields(get, m, n, T, ph, v4);
       }
-      const C2 v4[4] = {phi, zeta, U, V};
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         vals[bb * 8 + 2 * f] = (R)v4[f].x;
         vals[bb * 8 + 2 * f + 1] = (R)v4[f].y;
       }
     }
-    const int p = (n - m) & 1, i = (n - m) >> 1;
-    const MPInfo q = mpi[2 * m + p];
-    const int KB = Op::KB;
-    const long long blk = q.xS + (long long)(i / KB) * CBs + (b0 * 8) / 16;
-    const int kk = i % KB;
-    if constexpr (Op::KIND == OP_BF16X3) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) Op::store(X, blk, (kk >> 3) * 16 + c, kk & 7, vals[c]);
-    } else {
-      R* dst = reinterpret_cast<R*>(X) + blk * 64 + kk * 16;   // 16 consecutive lanes
-      if constexpr (sizeof(R) == 4) {
-#pragma unroll
-        for (int c = 0; c < 16; c += 4)
-          *reinterpret_cast<float4*>(dst + c) = make_float4(vals[c], vals[c + 1], vals[c + 2], vals[c + 3]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 16; c += 2)
-          *reinterpret_cast<double2*>(dst + c) = make_double2(vals[c], vals[c + 1]);
-      }
-    }
+    store_operand<Op>(X, mpi, m, n, CBs, b0, vals);
   }
 }
 
@@ -170,43 +192,53 @@ __global__ void k_unpack_scalar(const R* __restrict__ Y, double* __restrict__ sp
 // F_E from the analysed products (Sec. 2, transform method):
 //   D[X,Y]_n = (1/a) [ i m X_n - ( -n eps_{n+1} Y_{n+1} + (n+1) eps_n Y_{n-1} ) ]
 //   N_zeta = -D[A,B], N_delta = D[B,-A] + n(n+1)/a^2 E_n, N_Phi = -D[C,D]
-// where X_n, Y_n are the weighted P-contractions (degrees to T+1).
+// where X_n, Y_n are the weighted P-contractions (degrees to T+1) of one slice,
+// Yb = [5 products][Kx] complex.
+template <typename R>
+__device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, int eoff, int m,
+                                              int n, int T, double a, C2 out[3]) {
+  const double ia = 1.0 / a;
+  auto get = [&](int f, int nn) -> C2 {
+    if (nn < m || nn > T + 1) return {0.0, 0.0};
+    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + nn - m);
+    return {(double)p[0], (double)p[1]};
+  };
+  const double cp = -(double)n * eps_nm(n + 1, m), cm = (double)(n + 1) * eps_nm(n, m);
+  // H-weighted parts: hY = cp Y_{n+1} + cm Y_{n-1}
+  const C2 An = get(0, n), Bn = get(1, n), Cn = get(2, n), En = get(4, n);
+  const C2 Ap = get(0, n + 1), Am = get(0, n - 1);
+  const C2 Bp = get(1, n + 1), Bm = get(1, n - 1);
+  const C2 Dp = get(3, n + 1), Dm = get(3, n - 1);
+  const C2 hB = {cp * Bp.x + cm * Bm.x, cp * Bp.y + cm * Bm.y};
+  const C2 hA = {cp * Ap.x + cm * Am.x, cp * Ap.y + cm * Am.y};
+  const C2 hD = {cp * Dp.x + cm * Dm.x, cp * Dp.y + cm * Dm.y};
+  // D[X,Y] = (1/a)(i m X - hY);  i m X = (-m X.y, m X.x)
+  const C2 dAB = {ia * (-m * An.y - hB.x), ia * (m * An.x - hB.y)};
+  const C2 dBmA = {ia * (-m * Bn.y + hA.x), ia * (m * Bn.x + hA.y)};
+  const C2 dCD = {ia * (-m * Cn.y - hD.x), ia * (m * Cn.x - hD.y)};
+  const double ke = (double)n * (n + 1) * ia * ia;
+  out[0] = {-dCD.x, -dCD.y};
+  out[1] = {-dAB.x, -dAB.y};
+  out[2] = {dBmA.x + ke * En.x, dBmA.y + ke * En.y};
+  if (m == 0) {
+    out[0].y = 0;
+    out[1].y = 0;
+    out[2].y = 0;
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(128) void k_assemble(const R* __restrict__ Y, double* __restrict__ fe,
                                                  long long fstride, int T, double a) {
   const int m = blockIdx.x, b = blockIdx.y;
   const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
   const int eoff = ext_off(T, m), off = spec_off(T, m);
-  const double ia = 1.0 / a;
   const R* Yb = Y + (size_t)b * 5 * Kx * 2;
-  auto get = [&](int f, int n) -> C2 {
-    if (n < m || n > T + 1) return {0.0, 0.0};
-    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + n - m);
-    return {(double)p[0], (double)p[1]};
-  };
   double* F = fe + (size_t)b * fstride * 2;
   for (int n = m + threadIdx.x; n <= T; n += blockDim.x) {
-    const double cp = -(double)n * eps_nm(n + 1, m), cm = (double)(n + 1) * eps_nm(n, m);
-    // H-weighted parts: hY = cp Y_{n+1} + cm Y_{n-1}
-    const C2 An = get(0, n), Bn = get(1, n), Cn = get(2, n), En = get(4, n);
-    const C2 Ap = get(0, n + 1), Am = get(0, n - 1);
-    const C2 Bp = get(1, n + 1), Bm = get(1, n - 1);
-    const C2 Dp = get(3, n + 1), Dm = get(3, n - 1);
-    const C2 hB = {cp * Bp.x + cm * Bm.x, cp * Bp.y + cm * Bm.y};
-    const C2 hA = {cp * Ap.x + cm * Am.x, cp * Ap.y + cm * Am.y};
-    const C2 hD = {cp * Dp.x + cm * Dm.x, cp * Dp.y + cm * Dm.y};
-    // D[X,Y] = (1/a)(i m X - hY);  i m X = (-m X.y, m X.x)
-    const C2 dAB = {ia * (-m * An.y - hB.x), ia * (m * An.x - hB.y)};
-    const C2 dBmA = {ia * (-m * Bn.y + hA.x), ia * (m * Bn.x + hA.y)};
-    const C2 dCD = {ia * (-m * Cn.y - hD.x), ia * (m * Cn.x - hD.y)};
-    const double ke = (double)n * (n + 1) * ia * ia;
-    C2 nphi = {-dCD.x, -dCD.y};
-    C2 nzeta = {-dAB.x, -dAB.y};
-    C2 ndelta = {dBmA.x + ke * En.x, dBmA.y + ke * En.y};
-    if (m == 0) { nphi.y = 0; nzeta.y = 0; ndelta.y = 0; }
-    st2(F + 2 * (off + n - m), nphi);
-    st2(F + 2 * (K + off + n - m), nzeta);
-    st2(F + 2 * (2 * K + off + n - m), ndelta);
+    C2 o[3];
+    assemble_mode(Yb, Kx, eoff, m, n, T, a, o);
+    for (int v = 0; v < 3; ++v) st2(F + 2 * ((size_t)v * K + off + n - m), o[v]);
   }
 }
 
@@ -248,93 +280,133 @@ struct SdcMat {
   int nn;
 };
 
-// S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j) - dt sum_{j=1}^{i-1} qE_ij F_E^j
-//       - dt sum_{j=1}^{i} qI_ij F_I^j + tau_i        (old F, i = 1..M)
-// i.e. every term of the node-i update that uses only the previous iterate.
-template <int NN>
-__global__ void k_sweep_pre(const double* __restrict__ th, const double* __restrict__ fe,
-                            const double* __restrict__ fi, const double* __restrict__ tau,
-                            double* __restrict__ S, int K, int batch, double dt, SdcMat sm) {
+// One node of the IMEX sweep in Q form (Sec. 4, eq. update), node = 1..M, on
+// [batch][nn][3][K] arrays, fused with the passes that border it:
+//  (a) asm >= 0: F_E at node `asm` from the analysed products Y (assemble_mode);
+//  (b) node == 1: S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j)
+//        - dt sum_{j=1}^{i-1} qE_ij F_E^j - dt sum_{j=1}^{i} qI_ij F_I^j + tau_i
+//      for i = 1..M, every term of the node-i update that uses only the
+//      previous iterate (S_i of i >= 2 kept in S for the later nodes);
+//  (c) b = S_node + dt sum_{j=1}^{node-1} (qE F_E^j + qI F_I^j) (new F), the
+//      implicit solve with beta = dt qI_{node,node}, Theta^node and
+//      F_I^node = L Theta^node;
+//  (d) the synthesis operand of Theta^node (prep_fields), reading the new
+//      states of this order from LDS.
+// One workgroup per (m, pair of slices).
+template <class Op, int NN>
+__global__ __launch_bounds__(128) void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
+                                                   double* __restrict__ fi,
+                                                   const double* __restrict__ tau,
+                                                   double* __restrict__ S,
+                                                   const typename Op::R* __restrict__ Y,
+                                                   void* __restrict__ X,
+                                                   const MPInfo* __restrict__ mpi, int T, int CBs,
+                                                   int batch, int node, int asm_node, double dt,
+                                                   SdcMat sm, Phys ph) {
+  typedef typename Op::R R;
   constexpr int nn = NN, M = NN - 1;
-  const long long tot = (long long)batch * 3 * K;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(idx / (3 * K));
-    const int vk = (int)(idx - (long long)b * 3 * K);
-    const size_t base = (size_t)b * nn * 3 * K;
-    C2 E[NN], I[NN];
+  extern __shared__ unsigned char smem_raw[];
+  C2* sh = reinterpret_cast<C2*>(smem_raw);            // [2 slices][3 vars][T+1-m]
+  const int m = blockIdx.x, b0 = 2 * blockIdx.y;
+  const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
+  const int off = spec_off(T, m), eoff = ext_off(T, m), nm = T + 1 - m;
+  const double beta = dt * sm.QI[node * nn + node];
+  for (int n = m + threadIdx.x; n <= T; n += blockDim.x) {
+    const int k = off + n - m;
+    const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
 #pragma unroll
-    for (int j = 0; j < nn; ++j) {
-      E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
-      I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
-    }
-    const C2 t0 = ld2(th + 2 * (base + vk));
-#pragma unroll
-    for (int i = 1; i <= M; ++i) {
-      double sx = 0, sy = 0;
-#pragma unroll
-      for (int j = 0; j < nn; ++j) {
-        double c = sm.Q[i * nn + j];
-        sx += c * (E[j].x + I[j].x);
-        sy += c * (E[j].y + I[j].y);
+    for (int bb = 0; bb < 2; ++bb) {
+      const int b = b0 + bb;
+      if (b >= batch) continue;
+      const size_t base = (size_t)b * nn * 3 * K;
+      if (asm_node >= 0) {
+        C2 o[3];
+        assemble_mode(Y + (size_t)b * 5 * Kx * 2, Kx, eoff, m, n, T, ph.a, o);
+        for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
       }
+      C2 rhs[3];
+      for (int v = 0; v < 3; ++v) {
+        const size_t vk = (size_t)v * K + k;
+        C2 r;
+        if (node == 1) {
+          C2 E[NN], I[NN];
 #pragma unroll
-      for (int j = 1; j < i; ++j) {
-        sx -= sm.QE[i * nn + j] * E[j].x;
-        sy -= sm.QE[i * nn + j] * E[j].y;
-      }
+          for (int j = 0; j < nn; ++j) {
+            E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
+            I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
+          }
+          const C2 t0 = ld2(th + 2 * (base + vk));
 #pragma unroll
-      for (int j = 1; j <= i; ++j) {
-        sx -= sm.QI[i * nn + j] * I[j].x;
-        sy -= sm.QI[i * nn + j] * I[j].y;
+          for (int i = 1; i <= M; ++i) {
+            double sx = 0, sy = 0;
+#pragma unroll
+            for (int j = 0; j < nn; ++j) {
+              const double c = sm.Q[i * nn + j];
+              sx += c * (E[j].x + I[j].x);
+              sy += c * (E[j].y + I[j].y);
+            }
+#pragma unroll
+            for (int j = 1; j < i; ++j) {
+              sx -= sm.QE[i * nn + j] * E[j].x;
+              sy -= sm.QE[i * nn + j] * E[j].y;
+            }
+#pragma unroll
+            for (int j = 1; j <= i; ++j) {
+              sx -= sm.QI[i * nn + j] * I[j].x;
+              sy -= sm.QI[i * nn + j] * I[j].y;
+            }
+            C2 si = {t0.x + dt * sx, t0.y + dt * sy};
+            if (tau) {
+              const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
+              si.x += tv.x;
+              si.y += tv.y;
+            }
+            if (i == 1)
+              r = si;
+            else
+              st2(S + 2 * (((size_t)b * M + (i - 1)) * 3 * K + vk), si);
+          }
+        } else {
+          r = ld2(S + 2 * (((size_t)b * M + (node - 1)) * 3 * K + vk));
+          for (int j = 1; j < node; ++j) {
+            const size_t o = base + (size_t)j * 3 * K + vk;
+            const C2 e = ld2(fe + 2 * o), f = ld2(fi + 2 * o);
+            const double ce = dt * sm.QE[node * nn + j], ci = dt * sm.QI[node * nn + j];
+            r.x += ce * e.x + ci * f.x;
+            r.y += ce * e.y + ci * f.y;
+          }
+        }
+        rhs[v] = r;
       }
-      C2 r = {t0.x + dt * sx, t0.y + dt * sy};
-      if (tau) {
-        const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
-        r.x += tv.x;
-        r.y += tv.y;
+      C2 x[3];
+      solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], x[0], x[1], x[2]);
+      C2 f[3];
+      linear_mode(lam, ph, x[0], x[1], x[2], f);
+      for (int v = 0; v < 3; ++v) {
+        const size_t o = base + ((size_t)node * 3 + v) * K + k;
+        st2(th + 2 * o, x[v]);
+        st2(fi + 2 * o, f[v]);
+        sh[(bb * 3 + v) * nm + (n - m)] = x[v];
       }
-      st2(S + 2 * (((size_t)b * M + (i - 1)) * 3 * K + vk), r);
     }
   }
-}
-
-// node i: b = S_i + dt sum_{j=1}^{i-1} (qE_ij F_E^j + qI_ij F_I^j) (new F), then the
-// implicit solve with beta = dt qI_ii, Theta^i and F_I^i = L Theta^i.
-__global__ void k_sweep_node(double* __restrict__ th, const double* __restrict__ fe,
-                             double* __restrict__ fi, const double* __restrict__ S, int T,
-                             int batch, int node, double dt, SdcMat sm, Phys ph) {
-  const int K = (T + 1) * (T + 2) / 2, nn = sm.nn, M = nn - 1;
-  const long long tot = (long long)batch * K;
-  const double beta = dt * sm.QI[node * nn + node];
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(idx / K), k = (int)(idx - (long long)b * K);
-    int m, n;
-    slot_mn(T, k, m, n);
-    const size_t base = (size_t)b * nn * 3 * K;
-    C2 rhs[3];
-    for (int v = 0; v < 3; ++v) {
-      C2 r = ld2(S + 2 * (((size_t)b * M + (node - 1)) * 3 * K + (size_t)v * K + k));
-      for (int j = 1; j < node; ++j) {
-        const size_t o = base + (size_t)j * 3 * K + (size_t)v * K + k;
-        const C2 e = ld2(fe + 2 * o), f = ld2(fi + 2 * o);
-        const double ce = dt * sm.QE[node * nn + j], ci = dt * sm.QI[node * nn + j];
-        r.x += ce * e.x + ci * f.x;
-        r.y += ce * e.y + ci * f.y;
+  __syncthreads();
+  for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
+    R vals[16];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      C2 v4[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      if (b0 + bb < batch) {
+        auto get = [&](int v, int q) { return sh[(bb * 3 + v) * nm + (q - m)]; };
+        prep_fields(get, m, n, T, ph, v4);
       }
-      rhs[v] = r;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        vals[bb * 8 + 2 * f] = (R)v4[f].x;
+        vals[bb * 8 + 2 * f + 1] = (R)v4[f].y;
+      }
     }
-    const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
-    C2 xp, xz, xd;
-    solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], xp, xz, xd);
-    const size_t o = base + (size_t)node * 3 * K + k;
-    st2(th + 2 * o, xp);
-    st2(th + 2 * (o + K), xz);
-    st2(th + 2 * (o + 2 * K), xd);
-    st2(fi + 2 * o, {-ph.phibar * xd.x + ph.nu * lam * xp.x, -ph.phibar * xd.y + ph.nu * lam * xp.y});
-    st2(fi + 2 * (o + K), {ph.nu * lam * xz.x, ph.nu * lam * xz.y});
-    st2(fi + 2 * (o + 2 * K), {-lam * xp.x + ph.nu * lam * xd.x, -lam * xp.y + ph.nu * lam * xd.y});
+    store_operand<Op>(X, mpi, m, n, CBs, b0, vals);
   }
 }
 
@@ -679,24 +751,37 @@ hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double
     default: CALL(9); break;     \
   }
 
-hipError_t launch_sweep_pre(const pfsh_level* lv, double dt, const double* theta, const double* fe,
-                            const double* fi, const double* tau, int batch, hipStream_t s) {
-  const long long work = (long long)batch * 3 * lv->K;
-  const SdcMat sm = sdc_of(lv);
-#define PFSH_PRE(NN)                                                                           \
-  hipLaunchKernelGGL(k_sweep_pre<NN>, dim3(nblocks(work, 256)), dim3(256), 0, s, theta, fe, fi, \
-                     tau, lv->S, lv->K, batch, dt, sm)
-  PFSH_NN_SWITCH(lv->nn, PFSH_PRE)
-#undef PFSH_PRE
+template <class Op, int NN>
+static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, double dt,
+                                  double* th, double* fe, double* fi, const double* tau, int batch,
+                                  hipStream_t s) {
+  const size_t shm = (size_t)2 * 3 * (lv->T + 1) * sizeof(C2);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L, (batch + 1) / 2), dim3(128), shm, s, th,
+                     fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
+                     lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv));
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_node(const pfsh_level* lv, int node, double dt, double* theta,
-                             const double* fe, double* fi, int batch, hipStream_t s) {
-  const long long work = (long long)batch * lv->K;
-  hipLaunchKernelGGL(k_sweep_node, dim3(nblocks(work, 256)), dim3(256), 0, s, theta, fe, fi,
-                     lv->S, lv->T, batch, node, dt, sdc_of(lv), phys_of(lv));
-  return hipGetLastError();
+template <class Op>
+static hipError_t sweep_step_op(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
+                                double* fe, double* fi, const double* tau, int batch,
+                                hipStream_t s) {
+#define PFSH_STEP(NN) return sweep_step_impl<Op, NN>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s)
+  PFSH_NN_SWITCH(lv->nn, PFSH_STEP)
+#undef PFSH_STEP
+  return hipSuccess;
+}
+
+hipError_t launch_sweep_step(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
+                             double* fe, double* fi, const double* tau, int batch, hipStream_t s) {
+  switch (lv->op) {
+    case OP_F64: return sweep_step_op<OpF64>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s);
+    case OP_F32: return sweep_step_op<OpF32>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s);
+    default: return sweep_step_op<OpBF3>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s);
+  }
 }
 
 hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,

@@ -8,13 +8,6 @@
 
 #include "pfsh_internal.h"
 
-namespace pfsh {
-hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
-                       long long fes, double* fi, long long fis, int batch, hipStream_t s);
-hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s);
-}  // namespace pfsh
-
 using namespace pfsh;
 
 struct pfsh_pfasst {
@@ -115,9 +108,9 @@ hipError_t predict(pfsh_pfasst* x, double dt, const double* th0, double* thf, do
     if (j >= 1) {
       const double* src = x->thc + 2 * ((size_t)(b0 - mem) * z.stc + (size_t)Mc * z.n3kc);
       PF_TRY(launch_copy_state(src, z.stc, th, z.stc, z.n3kc, nb, s));
-      PF_TRY(rhs_strided(x->c, th, z.stc, fe, z.stc, fi, z.stc, nb, s));
+      PF_TRY(rhs_pending(x->c, th, z.stc, fi, z.stc, nb, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s));
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s, j >= 1));
   }
   // fine prediction and its F at all nodes
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->base, thf, B, s));
@@ -148,9 +141,9 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     if (n >= 1) {
       const double* src = x->thc + 2 * ((size_t)(n - 1) * mem * z.stc + (size_t)Mc * z.n3kc);
       PF_TRY(launch_copy_state(src, z.stc, th, z.stc, z.n3kc, mem, s));
-      PF_TRY(rhs_strided(x->c, th, z.stc, fe, z.stc, fi, z.stc, mem, s));
+      PF_TRY(rhs_pending(x->c, th, z.stc, fi, z.stc, mem, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s));
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s, n >= 1));
   }
   // D) interpolate the coarse increments; new fine initial conditions
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->tthc, thf, B, s));
@@ -211,15 +204,21 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
                           x->tau + oc, nb, s));
     // C) coarse initial conditions from the left neighbours (super-step t-1),
     //    coarse F at node 0, coarse sweeps, send
+    //    (when every step of the range takes a new initial condition, its F_E
+    //    assembly is left to the sweep's first node kernel)
     const int r_lo = std::max(b_lo, 1);
+    const bool pend = r_lo == b_lo;
     if (r_lo <= b_hi) {
       const int nr = (b_hi - r_lo + 1) * mem;
       const size_t ocr = (size_t)r_lo * mem * fc;
       PF_TRY(launch_copy_state(cm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kc, z.n3kc,
                                x->thc + ocr, z.stc, z.n3kc, nr, s));
-      PF_TRY(rhs_strided(x->c, x->thc + ocr, z.stc, x->fec + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
+      if (pend)
+        PF_TRY(rhs_pending(x->c, x->thc + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
+      else
+        PF_TRY(rhs_strided(x->c, x->thc + ocr, z.stc, x->fec + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s));
+    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s, pend));
     PF_TRY(launch_copy_state(x->thc + oc + 2 * (size_t)Mc * z.n3kc, z.stc, cm_now + omc, z.n3kc,
                              z.n3kc, nb, s));
     // D) interpolate the coarse increments, new fine initial conditions, fine F

@@ -157,10 +157,21 @@ hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fe_st
                            hipStream_t s);
 hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double* b, double* x,
                                  int batch, hipStream_t s);
-hipError_t launch_sweep_pre(const pfsh_level* lv, double dt, const double* theta, const double* fe,
-                            const double* fi, const double* tau, int batch, hipStream_t s);
-hipError_t launch_sweep_node(const pfsh_level* lv, int node, double dt, double* theta,
-                             const double* fe, double* fi, int batch, hipStream_t s);
+// Compositions of the kernels above (api.cpp): the RHS of strided states; the
+// RHS up to the analysis (F_E left in Y for the next sweep's first node
+// kernel); one sweep, optionally assembling a pending node-0 F_E first.
+hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
+                       long long fes, double* fi, long long fis, int batch, hipStream_t s);
+hipError_t rhs_pending(const pfsh_level* lv, const double* state, long long sstride, double* fi,
+                       long long fis, int batch, hipStream_t s);
+hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
+                      const double* tau, int batch, hipStream_t s, bool node0_pending = false);
+
+// Sweep node `node` (1..M) fused with the F_E assembly of node `asm_node`
+// (-1: none), the old-iterate accumulation (node 1) and the synthesis input of
+// the new node state; leaves the analysis of that state to the caller.
+hipError_t launch_sweep_step(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
+                             double* fe, double* fi, const double* tau, int batch, hipStream_t s);
 hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
                            const double* fi, const double* tau, double* out, int batch,
                            hipStream_t s);
