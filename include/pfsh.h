@@ -215,12 +215,14 @@ pfsh_status pfsh_profile_read(pfsh_level* level, int kernel, int* launches, doub
  * The Legendre variants give bitwise identical results (same order of every
  * sum); the ring variants differ in FFT round-off only.
  * pfsh_level_autotune times every variant of the three stages at `batch`
- * (one warm-up and `reps` launches each, HIP events on `stream`) on the
- * level's internal workspace, and keeps the fastest for that batch's buckets.
+ * (three interleaved rounds of one warm-up and `reps` launches each, HIP
+ * events on `stream`, best round per variant) on the level's internal
+ * workspace, and keeps for that batch's buckets the fastest variant if it
+ * beats the default by at least 3%, else the default.
  * It synchronizes the stream, overwrites the level's workspace (which holds
  * nothing between calls), and returns PFSH_EUNSUPPORTED while the stream is
  * being captured; graphs captured earlier keep the variants they recorded.
- * us_out (host, nullable) receives the microseconds per launch at
+ * us_out (host, nullable) receives the best microseconds per launch at
  * [stage * PFSH_MAX_VARIANTS + variant].  One level must not be tuned and
  * used on two streams at once.
  * ------------------------------------------------------------------------- */

@@ -292,9 +292,10 @@ struct SdcMat {
 //      F_I^node = L Theta^node;
 //  (d) the synthesis operand of Theta^node (prep_fields), reading the new
 //      states of this order from LDS.
-// One workgroup per (m, pair of slices).
+// One workgroup of 256 threads per (m, pair of slices): the (slice, degree)
+// pairs of (a)-(c) are spread over all threads, (d) takes one degree per thread.
 template <class Op, int NN>
-__global__ __launch_bounds__(128) void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
+__global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
                                                    double* __restrict__ fi,
                                                    const double* __restrict__ tau,
                                                    double* __restrict__ S,
@@ -311,13 +312,13 @@ __global__ __launch_bounds__(128) void k_sweep_step(double* __restrict__ th, dou
   const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
   const int off = spec_off(T, m), eoff = ext_off(T, m), nm = T + 1 - m;
   const double beta = dt * sm.QI[node * nn + node];
-  for (int n = m + threadIdx.x; n <= T; n += blockDim.x) {
+  const int nsl = min(2, batch - b0);                  // slices of this workgroup
+  for (int it = threadIdx.x; it < nsl * nm; it += blockDim.x) {
+    const int bb = it / nm, n = m + (it - bb * nm);
+    const int b = b0 + bb;
     const int k = off + n - m;
     const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
-      const int b = b0 + bb;
-      if (b >= batch) continue;
+    {
       const size_t base = (size_t)b * nn * 3 * K;
       if (asm_node >= 0) {
         C2 o[3];
@@ -759,7 +760,7 @@ static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, 
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L, (batch + 1) / 2), dim3(128), shm, s, th,
+  hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L, (batch + 1) / 2), dim3(256), shm, s, th,
                      fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
                      lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv));
   return hipGetLastError();

@@ -56,7 +56,7 @@ def test_autotune_keeps_a_valid_choice_and_results():
             assert len(us) == gl.variant_count(stage)
             assert 0 <= chosen < len(us)
             assert all(t > 0 for t in us), (stage, us)
-            assert us[chosen] == min(us)
+            assert us[chosen] == min(us) or (chosen == 0 and min(us) > 0.97 * us[0])
     fe = _rhs(gl, to_dev(states))
     for b in range(B):
         assert np.all(rel_err(fe[b], swe.explicit_rhs(ol, states[b])) <= 1e-12)
