@@ -40,8 +40,22 @@ METRIC = "SDC sweeps/s at T255 x16 slices: mixed vs FP64 at <=1e-6 rel err; SHT 
 FINE = (255, 384, 768, 5)
 COARSE = (127, 192, 384, 3)
 N_TS = 16
+MEMBERS = 1
+POWER = 2.0
 DT = 60.0
 SEED = 3
+SEEDS = (SEED,)
+WORKLOAD = "pfasst_t255_t127_16slices"
+
+# The large-ensemble workload (--workload ensemble): T511 / T255, 32 steps x 4
+# members with n^-3 spectra, 4 iterations, FP32 fine transforms throughout.
+ENSEMBLE = dict(FINE=(511, 768, 1536, 5), COARSE=(255, 384, 768, 3), N_TS=32, MEMBERS=4,
+                POWER=3.0, SEEDS=(500, 501, 502, 503), WORKLOAD="pfasst_t511_t255_32x4_ensemble")
+
+
+def initial_states(inputs):
+    """[members, 3, K] seeded initial states of the workload."""
+    return inputs.seeded_batch(FINE[0], SEEDS, POWER)
 PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}   # dense MFMA TFLOP/s
 HBM_PEAK = 8000.0  # GB/s
 
@@ -69,13 +83,13 @@ def rhs_sht_flops(T, nlat, nlon, batch):
             + ring_flops(nlat, nlon, batch))
 
 
-def block_sht_flops(fine, coarse, n_ts, n_pf):
+def block_sht_flops(fine, coarse, n_ts, n_pf, members=1):
     """Algorithmic SHT flops of one PFASST block (predictor + n_pf iterations,
     the last stopping after the fine sweep), counted per RHS evaluation."""
     Tf, nlf, nof, nnf = fine
     Tc, nlc, noc, nnc = coarse
-    fr = lambda b: rhs_sht_flops(Tf, nlf, nof, b)
-    cr = lambda b: rhs_sht_flops(Tc, nlc, noc, b)
+    fr = lambda b: rhs_sht_flops(Tf, nlf, nof, b * members)
+    cr = lambda b: rhs_sht_flops(Tc, nlc, noc, b * members)
     f = cr(n_ts)                                                # predictor: coarse F at the IC
     for j in range(n_ts):                                       # wavefront stages
         if j >= 1:
@@ -106,12 +120,12 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
     dev = torch.device("cuda", 0)
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
-    B = N_TS
+    B = N_TS * MEMBERS
     gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=mixed)
     gc = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B)
-    gf64 = gfm if mixed == "fp64" else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
-    pf = pfsh.Pfasst(gfm, gc, N_TS)
-    th0 = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to(dev)
+    gf64 = gfm if (mixed == "fp64" or n64 == 0) else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
+    pf = pfsh.Pfasst(gfm, gc, N_TS, MEMBERS)
+    th0 = torch.from_numpy(initial_states(inputs)).to(dev)
     thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
     res = torch.empty((B, 3), dtype=torch.float64, device=dev)
     k_switch = args.n_pf - n64
@@ -119,9 +133,10 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
     if not getattr(args, "no_tune", False):
         # the batches each level runs: fine sweeps of all slices (the wavefront
         # order also smaller groups), coarse batched steps and the serial chain
-        fine_b = [B] if args.schedule == "iterations" else [B, 8, 4, 2, 1]
+        fine_b = [B] if args.schedule == "iterations" else sorted({B, 8, 4, 2, 1}, reverse=True)
+        coarse_b = sorted({MEMBERS, 2 * MEMBERS, 4 * MEMBERS, 8 * MEMBERS, B} & set(range(1, B + 1)))
         for name, lv, batches in (("fine", gfm, fine_b), ("fine_fp64", gf64, fine_b),
-                                  ("coarse", gc, [1, 2, 4, 8, B])):
+                                  ("coarse", gc, coarse_b)):
             if name == "fine_fp64" and gf64 is gfm:
                 continue
             tuned[name] = {b: {k: v[0] for k, v in lv.autotune(b, reps=10).items()} for b in batches}
@@ -187,7 +202,7 @@ def run_states(args, mixed, n64, torch, pfsh, inputs):
     ctx = make_block(a, mixed, n64, pfsh, inputs, torch)
     pf, (gfm, gc, gf64) = ctx["pf"], ctx["levels"]
     thf, fef, fif = ctx["arrays"]
-    th0 = torch.from_numpy(inputs.seeded_state(FINE[0], SEED)[None]).to("cuda")
+    th0 = torch.from_numpy(initial_states(inputs)).to("cuda")
     pf.set_levels(gfm, gc)
     pf.predict(DT, th0, thf, fef, fif)
     out = []
@@ -204,11 +219,11 @@ def serial_reference(torch, pfsh, inputs, nsweeps=20):
     """Serial FP64 SDC on the fine level, step after step (collocation solution
     of every time step of the block, to which PFASST converges)."""
     Tf, nlf, nof, nnf = FINE
-    gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=1)
-    x = torch.from_numpy(inputs.seeded_state(Tf, SEED)[None]).to("cuda")
+    gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=MEMBERS)
+    x = torch.from_numpy(initial_states(inputs)).to("cuda")
     out = []
     for _ in range(N_TS):
-        th, fe, fi = gl.space_time(1), gl.space_time(1), gl.space_time(1)
+        th, fe, fi = gl.space_time(MEMBERS), gl.space_time(MEMBERS), gl.space_time(MEMBERS)
         e, i = gl.rhs(x)
         th[:, 0] = x
         fe[:, 0] = e
@@ -217,8 +232,14 @@ def serial_reference(torch, pfsh, inputs, nsweeps=20):
         for _ in range(nsweeps):
             gl.sdc_sweep(DT, th, fe, fi)
         x = th[:, -1].contiguous()
-        out.append(x[0].cpu().numpy())
-    return np.array(out)
+        out.append(x.cpu().numpy())
+    return np.concatenate(out)       # [step * members + member]
+
+
+def rel_err_slices(a, b):
+    """The paper's normalized max-norm error per variable, each slice (time
+    step, member) normalized by its own reference; the maximum over slices."""
+    return [float(x) for x in np.max([rel_err(a[s:s + 1], b[s:s + 1]) for s in range(len(a))], axis=0)]
 
 
 def rel_err(a, b):
@@ -242,7 +263,7 @@ def cpu_baseline(seconds_budget=20.0):
     Tc, nlc, noc, nnc = COARSE
     lf, lc = swe.Level(Tf, nlf, nof), swe.Level(Tc, nlc, noc)
     sf, sc = sdc.SDC(nnf), sdc.SDC(nnc)
-    x0 = inputs.seeded_state(Tf, SEED)
+    x0 = initial_states(inputs)[0]
     th, fe, fi = sdc.spread(lf, x0, nnf)
     done, wall0, cpu0 = 0, time.perf_counter(), time.process_time()
     while True:
@@ -258,15 +279,16 @@ def cpu_baseline(seconds_budget=20.0):
         i = i + transfer.interpolate(sc, sf, Tc, Tf, ic2 - ic)
         e[0], i[0] = swe.rhs(lf, t[0])
         done += 1
-        if time.perf_counter() - wall0 > seconds_budget or done >= N_TS:
+        if time.perf_counter() - wall0 > seconds_budget or done >= N_TS * MEMBERS:
             break
     wall = time.perf_counter() - wall0
     cpu = time.process_time() - cpu0
     per_slice = wall / done
-    return {"value": 1.0 / (per_slice * N_TS), "unit": "sweeps/s", "kind": "oracle",
+    nsl = N_TS * MEMBERS
+    return {"value": 1.0 / (per_slice * nsl), "unit": "sweeps/s", "kind": "oracle",
             "cores": max(1, int(round(cpu / wall))),
-            "sample": f"{done} of {N_TS} slices' share of one PFASST iteration at T255/T127 "
-                      f"({wall:.1f} s), scaled to all {N_TS} slices"}
+            "sample": f"{done} of {nsl} slices' share of one PFASST iteration at T{Tf}/T{Tc} "
+                      f"({wall:.1f} s), scaled to all {nsl} slices"}
 
 
 def main():
@@ -275,9 +297,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10, help="timed PFASST blocks")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16x3"])
-    ap.add_argument("--n64", type=int, default=4,
-                    help="final PFASST iterations with FP64 fine levels in the mixed block")
-    ap.add_argument("--n-pf", type=int, default=8, help="PFASST iterations per block")
+    ap.add_argument("--workload", default="t255", choices=["t255", "ensemble"],
+                    help="t255: T255/T127, 16 steps (the headline); ensemble: T511/T255, "
+                         "32 steps x 4 members")
+    ap.add_argument("--n64", type=int, default=None,
+                    help="final PFASST iterations with FP64 fine levels in the mixed block "
+                         "(default 4; ensemble 0)")
+    ap.add_argument("--n-pf", type=int, default=None,
+                    help="PFASST iterations per block (default 8; ensemble 4)")
     ap.add_argument("--schedule", default="iterations", choices=["wavefront", "iterations"],
                     help="order of the PFASST work inside a block (same arithmetic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -286,6 +313,12 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.workload == "ensemble":
+        globals().update(ENSEMBLE)
+    if args.n_pf is None:
+        args.n_pf = 8 if args.workload == "t255" else 4
+    if args.n64 is None:
+        args.n64 = 4 if args.workload == "t255" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (time slices are its batch axis); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -314,26 +347,28 @@ def main():
     smx = run_states(args, args.mixed, args.n64, torch, pfsh, inputs)
     spure = run_states(args, args.mixed, 0, torch, pfsh, inputs)
     x64, xmx, xpure = s64[-1], smx[-1], spure[-1]
-    err = rel_err(xmx, x64)
-    err_pure = rel_err(xpure, x64)
-    err_iter = [rel_err(a, b) for a, b in zip(smx, s64)]
-    err_iter_pure = [rel_err(a, b) for a, b in zip(spure, s64)]
+    err = rel_err_slices(xmx, x64)
+    err_pure = rel_err_slices(xpure, x64)
+    err_iter = [rel_err_slices(a, b) for a, b in zip(smx, s64)]
+    err_iter_pure = [rel_err_slices(a, b) for a, b in zip(spure, s64)]
     xref = serial_reference(torch, pfsh, inputs)
 
     # dominant kernel of the mixed-precision fine level and its roofline
     prof = rpr["prof"]
     dom = max(prof, key=lambda k: prof[k][1])
     Tf, nlf, nof, nnf = FINE
+    Tc, nlc, noc, nnc = COARSE
+    B = N_TS * MEMBERS
     n, tot = prof[dom]
     avg_s = tot / max(n, 1) * 1e-3
     rsz = 8 if args.mixed == "fp64" else 4
     if dom in ("leg_synth", "leg_anal"):
-        ncols = (8 if dom == "leg_synth" else 10) * N_TS
+        ncols = (8 if dom == "leg_synth" else 10) * B
         work = legendre_flops(Tf, nlf, ncols)
         roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAKS[args.mixed],
                 "unit": "TFLOP/s"}
     else:
-        work = ring_bytes(Tf, nlf, rsz, N_TS)
+        work = ring_bytes(Tf, nlf, rsz, B)
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
@@ -341,19 +376,20 @@ def main():
     roof["launches"] = n
     roof["avg_us"] = avg_s * 1e6
 
-    sht = block_sht_flops(FINE, COARSE, N_TS, args.n_pf)
+    sht = block_sht_flops(FINE, COARSE, N_TS, args.n_pf, MEMBERS)
     value = args.n_pf * 1e3 / rmx["ms"]
     out = {
         "metric": METRIC, "value": value, "unit": "sweeps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": rmx["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": f"{args.mixed}+f64", "data": "synthetic",
-        "config": {"workload": "pfasst_t255_t127_16slices", "fine": "T255 384x768 5 Lobatto nodes",
-                   "coarse": "T127 192x384 3 nodes", "slices": N_TS, "dt_s": DT,
+        "config": {"workload": WORKLOAD, "fine": f"T{Tf} {nlf}x{nof} {nnf} Lobatto nodes",
+                   "coarse": f"T{Tc} {nlc}x{noc} {nnc} nodes", "slices": N_TS,
+                   "members": MEMBERS, "spectrum": f"n^-{POWER:g}", "dt_s": DT,
                    "n_pf": args.n_pf, "fp64_final_iterations": args.n64,
                    "schedule": args.schedule, "coarse_precision": "fp64",
                    "step": "one PFASST block: predictor + n_pf iterations, fine residual",
-                   "seed": SEED, "parallelism": "slices as batch, 1 GPU"},
+                   "seeds": list(SEEDS), "parallelism": "slices x members as batch, 1 GPU"},
         "roofline": roof,
         "fp64": {"sweeps_per_s": args.n_pf * 1e3 / r64["ms"], "ms_per_step": r64["ms"],
                  "sweep_only_ms": r64["sweep_ms"],
@@ -363,8 +399,9 @@ def main():
         "mixed_without_fp64_iterations_rel_err": err_pure,
         "mixed_rel_err_per_iteration": err_iter,
         "mixed_without_fp64_iterations_rel_err_per_iteration": err_iter_pure,
-        "pfasst_err_vs_serial_collocation": {"fp64": rel_err(x64, xref), "mixed": rel_err(xmx, xref),
-                                             "mixed_without_fp64_iterations": rel_err(xpure, xref)},
+        "pfasst_err_vs_serial_collocation": {
+            "fp64": rel_err_slices(x64, xref), "mixed": rel_err_slices(xmx, xref),
+            "mixed_without_fp64_iterations": rel_err_slices(xpure, xref)},
         "sweep_only_ms": rmx["sweep_ms"],
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},

@@ -51,12 +51,14 @@ static hipError_t transforms(const pfsh_level* lv, int batch, hipStream_t s) {
 
 // F_I of `batch` states spaced `sstride` complex values apart (when fi is not
 // null) and the transforms of F_E up to the analysis; F_E itself is assembled
-// by the next sweep's first node kernel.
+// by the next sweep's first node kernel.  copy_to (nullable): the states are
+// also copied there (stride copy_stride).
 hipError_t rhs_pending(const pfsh_level* lv, const double* state, long long sstride, double* fi,
-                       long long fis, int batch, hipStream_t s) {
+                       long long fis, int batch, hipStream_t s, double* copy_to,
+                       long long copy_stride) {
   {
     ProfScope p(lv, PFSH_K_PREP, s);
-    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
+    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s, copy_to, copy_stride));
   }
   return transforms(lv, batch, s);
 }

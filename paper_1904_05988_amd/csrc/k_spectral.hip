@@ -110,10 +110,11 @@ __device__ __forceinline__ void linear_mode(double lam, Phys ph, C2 p, C2 z, C2 
 }
 
 // One workgroup per (m, pair of slices): the synthesis operand of the states
-// (and optionally F_I = L(Theta) per mode).
+// (and optionally F_I = L(Theta) per mode, and a copy of the states to `cp`).
 template <class Op>
 __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th, long long sstride,
                                                  double* __restrict__ fi, long long fstride,
+                                                 double* __restrict__ cp, long long cstride,
                                                  void* __restrict__ X, const MPInfo* __restrict__ mpi,
                                                  int T, int CBs, int batch, Phys ph) {
   typedef typename Op::R R;
@@ -135,6 +136,10 @@ __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th,
           linear_mode(lam, ph, get(0, n), get(1, n), get(2, n), f);
           double* F = fi + (size_t)b * fstride * 2;
           for (int v = 0; v < 3; ++v) st2(F + 2 * ((size_t)v * K + off + n - m), f[v]);
+        }
+        if (cp && n <= T) {
+          double* C = cp + (size_t)b * cstride * 2;
+          for (int v = 0; v < 3; ++v) st2(C + 2 * ((size_t)v * K + off + n - m), get(v, n));
         }
         prep_fields(get, m, n, T, ph, v4);
       }
@@ -673,20 +678,21 @@ static inline SdcMat sdc_of(const pfsh_level* lv) {
 }
 
 hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long sstride,
-                           double* f_impl, long long fstride, int batch, hipStream_t s) {
+                           double* f_impl, long long fstride, int batch, hipStream_t s,
+                           double* copy_to, long long cstride) {
   dim3 grid(lv->L, (batch + 1) / 2);
   switch (lv->op) {
     case OP_F64:
       hipLaunchKernelGGL(k_prep_rhs<OpF64>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
+                         fstride, copy_to, cstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     case OP_F32:
       hipLaunchKernelGGL(k_prep_rhs<OpF32>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
+                         fstride, copy_to, cstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     default:
       hipLaunchKernelGGL(k_prep_rhs<OpBF3>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
+                         fstride, copy_to, cstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
   }
   return hipGetLastError();
 }

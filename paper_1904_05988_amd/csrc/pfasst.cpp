@@ -107,8 +107,7 @@ hipError_t predict(pfsh_pfasst* x, double dt, const double* th0, double* thf, do
     double* fi = x->fic + 2 * (size_t)b0 * z.stc;
     if (j >= 1) {
       const double* src = x->thc + 2 * ((size_t)(b0 - mem) * z.stc + (size_t)Mc * z.n3kc);
-      PF_TRY(launch_copy_state(src, z.stc, th, z.stc, z.n3kc, nb, s));
-      PF_TRY(rhs_pending(x->c, th, z.stc, fi, z.stc, nb, s));
+      PF_TRY(rhs_pending(x->c, src, z.stc, fi, z.stc, nb, s, th, z.stc));
     }
     PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s, j >= 1));
   }
@@ -140,8 +139,7 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     double* fi = x->fic + o;
     if (n >= 1) {
       const double* src = x->thc + 2 * ((size_t)(n - 1) * mem * z.stc + (size_t)Mc * z.n3kc);
-      PF_TRY(launch_copy_state(src, z.stc, th, z.stc, z.n3kc, mem, s));
-      PF_TRY(rhs_pending(x->c, th, z.stc, fi, z.stc, mem, s));
+      PF_TRY(rhs_pending(x->c, src, z.stc, fi, z.stc, mem, s, th, z.stc));
     }
     PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s, n >= 1));
   }
@@ -211,12 +209,13 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
     if (r_lo <= b_hi) {
       const int nr = (b_hi - r_lo + 1) * mem;
       const size_t ocr = (size_t)r_lo * mem * fc;
-      PF_TRY(launch_copy_state(cm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kc, z.n3kc,
-                               x->thc + ocr, z.stc, z.n3kc, nr, s));
-      if (pend)
-        PF_TRY(rhs_pending(x->c, x->thc + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
-      else
+      const double* src = cm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kc;
+      if (pend) {
+        PF_TRY(rhs_pending(x->c, src, z.n3kc, x->fic + ocr, z.stc, nr, s, x->thc + ocr, z.stc));
+      } else {
+        PF_TRY(launch_copy_state(src, z.n3kc, x->thc + ocr, z.stc, z.n3kc, nr, s));
         PF_TRY(rhs_strided(x->c, x->thc + ocr, z.stc, x->fec + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
+      }
     }
     PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s, pend));
     PF_TRY(launch_copy_state(x->thc + oc + 2 * (size_t)Mc * z.n3kc, z.stc, cm_now + omc, z.n3kc,

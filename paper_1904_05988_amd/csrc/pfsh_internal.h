@@ -150,7 +150,8 @@ hipError_t launch_ring_anal(const pfsh_level* lv, int nfields, const double* gri
 
 // spectral kernels (FP64)
 hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long state_stride,
-                           double* f_impl, long long fi_stride, int batch, hipStream_t s);
+                           double* f_impl, long long fi_stride, int batch, hipStream_t s,
+                           double* copy_to = nullptr, long long copy_stride = 0);
 hipError_t launch_prep_scalar(const pfsh_level* lv, const double* spec, int nfields, hipStream_t s);
 hipError_t launch_unpack_scalar(const pfsh_level* lv, double* spec, int nfields, hipStream_t s);
 hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fe_stride, int batch,
@@ -163,7 +164,8 @@ hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s);
 hipError_t rhs_pending(const pfsh_level* lv, const double* state, long long sstride, double* fi,
-                       long long fis, int batch, hipStream_t s);
+                       long long fis, int batch, hipStream_t s, double* copy_to = nullptr,
+                       long long copy_stride = 0);
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
                       const double* tau, int batch, hipStream_t s, bool node0_pending = false);
 
