@@ -49,29 +49,16 @@ static hipError_t transforms(const pfsh_level* lv, int batch, hipStream_t s) {
   return launch_leg_anal(lv, 2 * 5 * batch, 5, s);
 }
 
-// F_I of `batch` states spaced `sstride` complex values apart (when fi is not
-// null) and the transforms of F_E up to the analysis; F_E itself is assembled
-// by the next sweep's first node kernel.  copy_to (nullable): the states are
-// also copied there (stride copy_stride).
-hipError_t rhs_pending(const pfsh_level* lv, const double* state, long long sstride, double* fi,
-                       long long fis, int batch, hipStream_t s, double* copy_to,
-                       long long copy_stride) {
-  {
-    ProfScope p(lv, PFSH_K_PREP, s);
-    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s, copy_to, copy_stride));
-  }
-  return transforms(lv, batch, s);
-}
-
 // F_E (and optionally F_I) at `batch` states spaced `sstride` complex values
 // apart; outputs spaced fes / fis apart.
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s) {
-  if (!fe) {
+  {
     ProfScope p(lv, PFSH_K_PREP, s);
-    return launch_prep_rhs(lv, state, sstride, fi, fis, batch, s);
+    PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
   }
-  PFSH_TRY(rhs_pending(lv, state, sstride, fi, fis, batch, s));
+  if (!fe) return hipSuccess;
+  PFSH_TRY(transforms(lv, batch, s));
   ProfScope p(lv, PFSH_K_ASSEMBLE, s);
   return launch_assemble(lv, fe, fes, batch, s);
 }
@@ -80,14 +67,13 @@ hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstr
 // fused node kernel (update, implicit solve, F_I, synthesis input; on node 1
 // also the old-iterate terms) and the transforms of the new state; the F_E
 // assembly of each node runs in the next node's kernel, the last one on its
-// own.  node0_pending: F_E at node 0 is still in the analysis workspace
-// (rhs_pending ran on the node-0 state) and node 1's kernel assembles it.
+// own.
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s, bool node0_pending) {
+                      const double* tau, int batch, hipStream_t s) {
   const long long n3k = 3LL * lv->K;
   const long long stride = lv->nn * n3k;
   for (int i = 1; i <= lv->M; ++i) {
-    const int asm_node = i > 1 ? i - 1 : (node0_pending ? 0 : -1);
+    const int asm_node = i > 1 ? i - 1 : -1;
     {
       ProfScope p(lv, PFSH_K_SWEEP_NODE, s);
       PFSH_TRY(launch_sweep_step(lv, i, asm_node, dt, th, fe, fi, tau, batch, s));

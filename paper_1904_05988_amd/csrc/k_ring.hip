@@ -129,8 +129,20 @@ __device__ __forceinline__ void butterfly(cpx<R>* a) {
   }
 }
 
+// a * w (SIGN > 0) or a * conj(w) (SIGN < 0)
+template <int SIGN, typename R>
+__device__ __forceinline__ cpx<R> cmul_s(cpx<R> a, cpx<R> w) {
+  if constexpr (SIGN > 0) return {a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+  else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+
 // One Stockham stage on NSIG padded signals of length N stored back to back
-// in buf (stride padded_len(N)); tw[t] = e^{2 pi i t / N}.
+// in buf (stride padded_len(N)); tw[t] = e^{2 pi i t / N}.  Element i of a
+// signal sits at padded(i).  When the RAD inputs j + r NB of a butterfly (and
+// its outputs base + r NS) stay in step with the padding -- NB (NS) a multiple
+// of 16, or an output run of RAD | 16 elements aligned to RAD -- their padded
+// addresses are one base plus r times a constant, so the LDS accesses take
+// immediate offsets instead of per-element index arithmetic.
 template <typename R, int N, int RAD, int NSIG, int NT, int SIGN, int NS>
 __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int NB = N / RAD;
@@ -138,6 +150,10 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int PER = (TOT + NT - 1) / NT;
   constexpr int STEP = N / (NS * RAD);
   constexpr int SP = padded_len(N);
+  constexpr bool kInConst = NB % 16 == 0;
+  constexpr bool kOutConst = NS % 16 == 0 || (NS == 1 && 16 % RAD == 0);
+  constexpr int IN_STRIDE = padded_len(NB);
+  constexpr int OUT_STRIDE = NS % 16 == 0 ? padded_len(NS) : 1;
   cpx<R> v[PER][RAD];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -145,15 +161,18 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
     if (TOT % NT == 0 || t < TOT) {
       const int sig = t / NB, j = t - sig * NB, k = j % NS;
       const cpx<R>* b = buf + sig * SP;
+      if constexpr (kInConst) {
+        const cpx<R>* pj = b + padded(j);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[q][r] = b[padded(j + r * NB)];
+        for (int r = 0; r < RAD; ++r) v[q][r] = pj[r * IN_STRIDE];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[q][r] = b[padded(j + r * NB)];
+      }
       if (NS > 1) {
+        const cpx<R>* tk = tw + k * STEP;
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          cpx<R> w = tw[r * k * STEP];
-          if (SIGN < 0) w.y = -w.y;
-          v[q][r] = cmul(v[q][r], w);
-        }
+        for (int r = 1; r < RAD; ++r) v[q][r] = cmul_s<SIGN>(v[q][r], tk[(r - 1) * k * STEP]);
       }
       butterfly<RAD, SIGN>(v[q]);
     }
@@ -166,8 +185,14 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
       const int sig = t / NB, j = t - sig * NB, k = j % NS;
       cpx<R>* b = buf + sig * SP;
       const int base = (j / NS) * NS * RAD + k;
+      if constexpr (kOutConst) {
+        cpx<R>* pb = b + padded(base);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) b[padded(base + r * NS)] = v[q][r];
+        for (int r = 0; r < RAD; ++r) pb[r * OUT_STRIDE] = v[q][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) b[padded(base + r * NS)] = v[q][r];
+      }
     }
   }
   __syncthreads();
@@ -182,8 +207,9 @@ __device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
   }
 }
 
-// Twiddles e^{2 pi i t / N}: staged in LDS for FP32 (small), read through the
-// cache from global memory for FP64.
+// Twiddles e^{2 pi i t / N}: staged in LDS for FP32, read through the cache
+// from global memory for FP64 (staging them measured slower there: the copy
+// per workgroup and the 16-byte LDS reads cost more than the cached loads).
 template <typename R, int N>
 struct Twiddles {
   static constexpr bool kLds = sizeof(R) == 4;

@@ -110,11 +110,10 @@ __device__ __forceinline__ void linear_mode(double lam, Phys ph, C2 p, C2 z, C2 
 }
 
 // One workgroup per (m, pair of slices): the synthesis operand of the states
-// (and optionally F_I = L(Theta) per mode, and a copy of the states to `cp`).
+// (and optionally F_I = L(Theta) per mode).
 template <class Op>
 __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th, long long sstride,
                                                  double* __restrict__ fi, long long fstride,
-                                                 double* __restrict__ cp, long long cstride,
                                                  void* __restrict__ X, const MPInfo* __restrict__ mpi,
                                                  int T, int CBs, int batch, Phys ph) {
   typedef typename Op::R R;
@@ -136,10 +135,6 @@ __global__ __launch_bounds__(128) void k_prep_rhs(const double* __restrict__ th,
           linear_mode(lam, ph, get(0, n), get(1, n), get(2, n), f);
           double* F = fi + (size_t)b * fstride * 2;
           for (int v = 0; v < 3; ++v) st2(F + 2 * ((size_t)v * K + off + n - m), f[v]);
-        }
-        if (cp && n <= T) {
-          double* C = cp + (size_t)b * cstride * 2;
-          for (int v = 0; v < 3; ++v) st2(C + 2 * ((size_t)v * K + off + n - m), get(v, n));
         }
         prep_fields(get, m, n, T, ph, v4);
       }
@@ -514,6 +509,23 @@ __global__ void k_copy_state(const double* __restrict__ src, long long sstride,
   }
 }
 
+// three arrays at once (state, F_E, F_I of one node), batch entries strided
+__global__ void k_copy_node3(const double* __restrict__ ts, const double* __restrict__ es,
+                             const double* __restrict__ is, long long sstride,
+                             double* __restrict__ td, double* __restrict__ ed,
+                             double* __restrict__ id, long long dstride, long long n_per,
+                             int batch) {
+  const long long tot = (long long)batch * n_per;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long b = idx / n_per, e = idx - b * n_per;
+    const long long so = 2 * (b * sstride + e), d = 2 * (b * dstride + e);
+    st2(td + d, ld2(ts + so));
+    st2(ed + d, ld2(es + so));
+    st2(id + d, ld2(is + so));
+  }
+}
+
 // -------------------------------------------------------------- transfers
 struct TMat {
   double P[81];  // [ndst][nsrc]
@@ -678,21 +690,20 @@ static inline SdcMat sdc_of(const pfsh_level* lv) {
 }
 
 hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long sstride,
-                           double* f_impl, long long fstride, int batch, hipStream_t s,
-                           double* copy_to, long long cstride) {
+                           double* f_impl, long long fstride, int batch, hipStream_t s) {
   dim3 grid(lv->L, (batch + 1) / 2);
   switch (lv->op) {
     case OP_F64:
       hipLaunchKernelGGL(k_prep_rhs<OpF64>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, copy_to, cstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     case OP_F32:
       hipLaunchKernelGGL(k_prep_rhs<OpF32>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, copy_to, cstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     default:
       hipLaunchKernelGGL(k_prep_rhs<OpBF3>, grid, dim3(128), 0, s, state, sstride, f_impl,
-                         fstride, copy_to, cstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
+                         fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
   }
   return hipGetLastError();
 }
@@ -812,6 +823,15 @@ hipError_t launch_spread(const pfsh_level* lv, double* a, int batch, hipStream_t
   const long long n3k = 3LL * lv->K;
   const long long work = (long long)batch * (lv->nn - 1) * n3k;
   hipLaunchKernelGGL(k_spread, dim3(nblocks(work, 256)), dim3(256), 0, s, a, lv->nn, n3k, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_node3(const double* ts, const double* es, const double* is,
+                             long long sstride, double* td, double* ed, double* id,
+                             long long dstride, long long n_per, int batch, hipStream_t s) {
+  const long long work = (long long)batch * n_per;
+  hipLaunchKernelGGL(k_copy_node3, dim3(nblocks(work, 256)), dim3(256), 0, s, ts, es, is, sstride,
+                     td, ed, id, dstride, n_per, batch);
   return hipGetLastError();
 }
 

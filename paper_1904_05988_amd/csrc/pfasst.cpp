@@ -24,7 +24,7 @@ struct pfsh_pfasst {
   double* base = nullptr;  // predictor: restricted spread initial condition
   double* snap = nullptr;  // fine last-node values sent in step A [B][3][Kf]
   double* fmail = nullptr; // wavefront: fine last-node values, two super-steps [2][B][3][Kf]
-  double* cmail = nullptr; // wavefront: coarse last-node values [2][B][3][Kc]
+  double* cmail = nullptr; // wavefront: coarse last-node state, F_E, F_I [2][B][3][3][Kc]
   bool graphs = false;     // replay captured iterations
   struct Cached {
     const void *thf, *fef, *fif;
@@ -99,17 +99,19 @@ hipError_t predict(pfsh_pfasst* x, double dt, const double* th0, double* thf, do
   PF_TRY(launch_spread(x->c, x->fec, B, s));
   PF_TRY(launch_spread(x->c, x->fic, B, s));
   // wavefront: stage j sweeps steps j..n_ts-1; step n >= 1 first takes the
-  // stage-(j-1) last-node value of step n-1
+  // stage-(j-1) last-node value of step n-1, with the F the stage-(j-1) sweep
+  // evaluated there (the same state on the same level: no new evaluation)
   for (int j = 0; j < x->n_ts; ++j) {
     const int b0 = j * mem, nb = B - b0;
     double* th = x->thc + 2 * (size_t)b0 * z.stc;
     double* fe = x->fec + 2 * (size_t)b0 * z.stc;
     double* fi = x->fic + 2 * (size_t)b0 * z.stc;
     if (j >= 1) {
-      const double* src = x->thc + 2 * ((size_t)(b0 - mem) * z.stc + (size_t)Mc * z.n3kc);
-      PF_TRY(rhs_pending(x->c, src, z.stc, fi, z.stc, nb, s, th, z.stc));
+      const size_t last = 2 * ((size_t)(b0 - mem) * z.stc + (size_t)Mc * z.n3kc);
+      PF_TRY(launch_copy_node3(x->thc + last, x->fec + last, x->fic + last, z.stc, th, fe, fi,
+                               z.stc, z.n3kc, nb, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s, j >= 1));
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s));
   }
   // fine prediction and its F at all nodes
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->base, thf, B, s));
@@ -137,11 +139,12 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     double* th = x->thc + o;
     double* fe = x->fec + o;
     double* fi = x->fic + o;
-    if (n >= 1) {
-      const double* src = x->thc + 2 * ((size_t)(n - 1) * mem * z.stc + (size_t)Mc * z.n3kc);
-      PF_TRY(rhs_pending(x->c, src, z.stc, fi, z.stc, mem, s, th, z.stc));
+    if (n >= 1) {   // receive: last-node state of step n-1 and the F there
+      const size_t last = 2 * ((size_t)(n - 1) * mem * z.stc + (size_t)Mc * z.n3kc);
+      PF_TRY(launch_copy_node3(x->thc + last, x->fec + last, x->fic + last, z.stc, th, fe, fi,
+                               z.stc, z.n3kc, mem, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s, n >= 1));
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s));
   }
   // D) interpolate the coarse increments; new fine initial conditions
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->tthc, thf, B, s));
@@ -187,8 +190,8 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
     const size_t of = (size_t)b_lo * mem * ff, oc = (size_t)b_lo * mem * fc;
     double* fm_now = x->fmail + (size_t)(t & 1) * x->B * 2 * z.n3kf;
     double* fm_prev = x->fmail + (size_t)((t + 1) & 1) * x->B * 2 * z.n3kf;
-    double* cm_now = x->cmail + (size_t)(t & 1) * x->B * 2 * z.n3kc;
-    double* cm_prev = x->cmail + (size_t)((t + 1) & 1) * x->B * 2 * z.n3kc;
+    double* cm_now = x->cmail + (size_t)(t & 1) * x->B * 2 * 3 * z.n3kc;
+    double* cm_prev = x->cmail + (size_t)((t + 1) & 1) * x->B * 2 * 3 * z.n3kc;
     const size_t omf = (size_t)b_lo * mem * 2 * z.n3kf, omc = (size_t)b_lo * mem * 2 * z.n3kc;
     PF_TRY(launch_copy_state(thf + of + 2 * (size_t)Mf * z.n3kf, z.stf, fm_now + omf, z.n3kf,
                              z.n3kf, nb, s));
@@ -200,26 +203,23 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
     PF_TRY(launch_copy_state(x->fic + oc, z.stc, x->tfic + oc, z.stc, z.stc, nb, s));
     PF_TRY(launch_fas_tau(x->f, x->c, dt, fef + of, fif + of, x->fec + oc, x->fic + oc,
                           x->tau + oc, nb, s));
-    // C) coarse initial conditions from the left neighbours (super-step t-1),
-    //    coarse F at node 0, coarse sweeps, send
-    //    (when every step of the range takes a new initial condition, its F_E
-    //    assembly is left to the sweep's first node kernel)
+    // C) coarse initial conditions (and the F there) from the left neighbours
+    //    (super-step t-1), coarse sweeps, send
     const int r_lo = std::max(b_lo, 1);
-    const bool pend = r_lo == b_lo;
     if (r_lo <= b_hi) {
       const int nr = (b_hi - r_lo + 1) * mem;
       const size_t ocr = (size_t)r_lo * mem * fc;
-      const double* src = cm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kc;
-      if (pend) {
-        PF_TRY(rhs_pending(x->c, src, z.n3kc, x->fic + ocr, z.stc, nr, s, x->thc + ocr, z.stc));
-      } else {
-        PF_TRY(launch_copy_state(src, z.n3kc, x->thc + ocr, z.stc, z.n3kc, nr, s));
-        PF_TRY(rhs_strided(x->c, x->thc + ocr, z.stc, x->fec + ocr, z.stc, x->fic + ocr, z.stc, nr, s));
-      }
+      const double* src = cm_prev + (size_t)(r_lo - 1) * mem * 2 * 3 * z.n3kc;
+      PF_TRY(launch_copy_node3(src, src + 2 * z.n3kc, src + 4 * z.n3kc, 3 * z.n3kc, x->thc + ocr,
+                               x->fec + ocr, x->fic + ocr, z.stc, z.n3kc, nr, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s, pend));
-    PF_TRY(launch_copy_state(x->thc + oc + 2 * (size_t)Mc * z.n3kc, z.stc, cm_now + omc, z.n3kc,
-                             z.n3kc, nb, s));
+    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s));
+    {
+      const size_t lastc = oc + 2 * (size_t)Mc * z.n3kc;
+      double* dst = cm_now + 3 * omc;
+      PF_TRY(launch_copy_node3(x->thc + lastc, x->fec + lastc, x->fic + lastc, z.stc, dst,
+                               dst + 2 * z.n3kc, dst + 4 * z.n3kc, 3 * z.n3kc, z.n3kc, nb, s));
+    }
     // D) interpolate the coarse increments, new fine initial conditions, fine F
     //    at node 0 (on the level of the next iteration)
     PF_TRY(launch_interp_add(x->c, x->f, x->thc + oc, x->tthc + oc, thf + of, nb, s));
@@ -272,7 +272,7 @@ extern "C" pfsh_status pfsh_pfasst_create(pfsh_level* f, pfsh_level* c, int n_ts
     if (e == hipSuccess) e = hipMalloc((void**)p, bc);
   if (e == hipSuccess) e = hipMalloc((void**)&x->snap, bf);
   if (e == hipSuccess) e = hipMalloc((void**)&x->fmail, 2 * bf);
-  if (e == hipSuccess) e = hipMalloc((void**)&x->cmail, 2 * (size_t)B * z.n3kc * 16);
+  if (e == hipSuccess) e = hipMalloc((void**)&x->cmail, 2 * (size_t)B * 3 * z.n3kc * 16);
   if (e == hipSuccess)
     for (double** p : bufs)
       if (e == hipSuccess) e = hipMemset(*p, 0, bc);

@@ -150,24 +150,19 @@ hipError_t launch_ring_anal(const pfsh_level* lv, int nfields, const double* gri
 
 // spectral kernels (FP64)
 hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long state_stride,
-                           double* f_impl, long long fi_stride, int batch, hipStream_t s,
-                           double* copy_to = nullptr, long long copy_stride = 0);
+                           double* f_impl, long long fi_stride, int batch, hipStream_t s);
 hipError_t launch_prep_scalar(const pfsh_level* lv, const double* spec, int nfields, hipStream_t s);
 hipError_t launch_unpack_scalar(const pfsh_level* lv, double* spec, int nfields, hipStream_t s);
 hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fe_stride, int batch,
                            hipStream_t s);
 hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double* b, double* x,
                                  int batch, hipStream_t s);
-// Compositions of the kernels above (api.cpp): the RHS of strided states; the
-// RHS up to the analysis (F_E left in Y for the next sweep's first node
-// kernel); one sweep, optionally assembling a pending node-0 F_E first.
+// Compositions of the kernels above (api.cpp): the RHS of strided states; one
+// sweep.
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s);
-hipError_t rhs_pending(const pfsh_level* lv, const double* state, long long sstride, double* fi,
-                       long long fis, int batch, hipStream_t s, double* copy_to = nullptr,
-                       long long copy_stride = 0);
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s, bool node0_pending = false);
+                      const double* tau, int batch, hipStream_t s);
 
 // Sweep node `node` (1..M) fused with the F_E assembly of node `asm_node`
 // (-1: none), the old-iterate accumulation (node 1) and the synthesis input of
@@ -188,6 +183,10 @@ hipError_t launch_fas_tau(const pfsh_level* f, const pfsh_level* c, double dt, c
 hipError_t launch_ic_correct(const pfsh_level* f, const pfsh_level* c, const double* recv_f,
                              long long recv_stride, const double* ic_c, long long ic_stride,
                              double* out_f, long long out_stride, int batch, hipStream_t s);
+// state, F_E and F_I of one node per batch entry in one launch
+hipError_t launch_copy_node3(const double* ts, const double* es, const double* is,
+                             long long sstride, double* td, double* ed, double* id,
+                             long long dstride, long long n_per, int batch, hipStream_t s);
 hipError_t launch_copy_state(const double* src, long long src_stride, double* dst,
                              long long dst_stride, long long n_per, int batch, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* v, int n, int* flag, hipStream_t s);
