@@ -121,8 +121,9 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
     B = N_TS * MEMBERS
-    gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=mixed)
-    gc = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B)
+    # workspaces for all nodes of all slices at once (F at every node in one call)
+    gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B * nnf, precision=mixed)
+    gc = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B * nnc)
     gf64 = gfm if (mixed == "fp64" or n64 == 0) else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
     pf = pfsh.Pfasst(gfm, gc, N_TS, MEMBERS)
     th0 = torch.from_numpy(initial_states(inputs)).to(dev)
@@ -135,7 +136,8 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
         # order also smaller groups), coarse batched steps and the serial chain
         fine_b = [B] if args.schedule == "iterations" else sorted({B, 8, 4, 2, 1}, reverse=True)
         coarse_b = sorted({MEMBERS, 2 * MEMBERS, 4 * MEMBERS, 8 * MEMBERS, B} & set(range(1, B + 1)))
-        for name, lv, batches in (("fine", gfm, fine_b), ("fine_fp64", gf64, fine_b),
+        coarse_b.append(B * nnc)
+        for name, lv, batches in (("fine", gfm, fine_b + [B * nnf]), ("fine_fp64", gf64, fine_b),
                                   ("coarse", gc, coarse_b)):
             if name == "fine_fp64" and gf64 is gfm:
                 continue
@@ -181,7 +183,8 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
         prof = None
         if profile:
             gfm.profile(False)
-            prof = {k: gfm.profile_read(k) for k in gfm.KERNELS}
+            # launches over the B slices (the one-off F at all nodes runs at B x nodes)
+            prof = {k: gfm.profile_read(k, batch=N_TS * MEMBERS) for k in gfm.KERNELS}
         s0 = time.perf_counter()
         for _ in range(10):
             gfm.sdc_sweep(DT, thf, fef, fif)

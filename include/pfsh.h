@@ -199,6 +199,9 @@ typedef enum {
 } pfsh_kernel_id;
 pfsh_status pfsh_profile_enable(pfsh_level* level, int on);
 pfsh_status pfsh_profile_read(pfsh_level* level, int kernel, int* launches, double* total_ms);
+/* the same restricted to launches over `batch` states (batch <= 0: all) */
+pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, int* launches,
+                                    double* total_ms);
 
 /* ---------------------------------------------------------------------------
  * Transform-kernel variants and the autotuner.  A level launches one variant

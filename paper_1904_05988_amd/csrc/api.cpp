@@ -38,14 +38,14 @@ namespace pfsh {
 // workspace Y.
 static hipError_t transforms(const pfsh_level* lv, int batch, hipStream_t s) {
   {
-    ProfScope p(lv, PFSH_K_LEG_SYNTH, s);
+    ProfScope p(lv, PFSH_K_LEG_SYNTH, s, batch);
     PFSH_TRY(launch_leg_synth(lv, 2 * 4 * batch, 4, s));
   }
   {
-    ProfScope p(lv, PFSH_K_RING, s);
+    ProfScope p(lv, PFSH_K_RING, s, batch);
     PFSH_TRY(launch_ring_rhs(lv, batch, s));
   }
-  ProfScope p(lv, PFSH_K_LEG_ANAL, s);
+  ProfScope p(lv, PFSH_K_LEG_ANAL, s, batch);
   return launch_leg_anal(lv, 2 * 5 * batch, 5, s);
 }
 
@@ -54,12 +54,12 @@ static hipError_t transforms(const pfsh_level* lv, int batch, hipStream_t s) {
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s) {
   {
-    ProfScope p(lv, PFSH_K_PREP, s);
+    ProfScope p(lv, PFSH_K_PREP, s, batch);
     PFSH_TRY(launch_prep_rhs(lv, state, sstride, fi, fis, batch, s));
   }
   if (!fe) return hipSuccess;
   PFSH_TRY(transforms(lv, batch, s));
-  ProfScope p(lv, PFSH_K_ASSEMBLE, s);
+  ProfScope p(lv, PFSH_K_ASSEMBLE, s, batch);
   return launch_assemble(lv, fe, fes, batch, s);
 }
 
@@ -67,20 +67,21 @@ hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstr
 // fused node kernel (update, implicit solve, F_I, synthesis input; on node 1
 // also the old-iterate terms) and the transforms of the new state; the F_E
 // assembly of each node runs in the next node's kernel, the last one on its
-// own.
+// own.  src: node 0 (state, F_E, F_I) is taken from there by node 1's kernel.
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s) {
+                      const double* tau, int batch, hipStream_t s, const StepSrc& src) {
   const long long n3k = 3LL * lv->K;
   const long long stride = lv->nn * n3k;
   for (int i = 1; i <= lv->M; ++i) {
     const int asm_node = i > 1 ? i - 1 : -1;
     {
-      ProfScope p(lv, PFSH_K_SWEEP_NODE, s);
-      PFSH_TRY(launch_sweep_step(lv, i, asm_node, dt, th, fe, fi, tau, batch, s));
+      ProfScope p(lv, PFSH_K_SWEEP_NODE, s, batch);
+      PFSH_TRY(launch_sweep_step(lv, i, asm_node, dt, th, fe, fi, tau, batch,
+                                 i == 1 ? src : StepSrc(), s));
     }
     PFSH_TRY(transforms(lv, batch, s));
   }
-  ProfScope p(lv, PFSH_K_ASSEMBLE, s);
+  ProfScope p(lv, PFSH_K_ASSEMBLE, s, batch);
   return launch_assemble(lv, fe + 2 * lv->M * n3k, stride, batch, s);
 }
 
@@ -232,6 +233,7 @@ static void prof_clear(pfsh_level* lv) {
     }
     v.clear();
   }
+  for (auto& v : lv->prof_batch) v.clear();
 }
 
 extern "C" pfsh_status pfsh_profile_enable(pfsh_level* lv, int on) {
@@ -245,17 +247,27 @@ extern "C" pfsh_status pfsh_profile_enable(pfsh_level* lv, int on) {
   return PFSH_OK;
 }
 
-extern "C" pfsh_status pfsh_profile_read(pfsh_level* lv, int kernel, int* launches, double* total_ms) {
+extern "C" pfsh_status pfsh_profile_read_batch(pfsh_level* lv, int kernel, int batch,
+                                               int* launches, double* total_ms) {
   if (!lv || kernel < 0 || kernel >= PFSH_K_COUNT) return PFSH_EINVAL;
   DeviceGuard g(lv->device);
   double sum = 0.0;
-  for (auto& pr : lv->prof[kernel]) {
-    if (hipEventSynchronize(pr.second) != hipSuccess) return PFSH_EHIP;
+  int n = 0;
+  const auto& ev = lv->prof[kernel];
+  const auto& bt = lv->prof_batch[kernel];
+  for (size_t i = 0; i < ev.size(); ++i) {
+    if (batch > 0 && bt[i] != batch) continue;
+    if (hipEventSynchronize(ev[i].second) != hipSuccess) return PFSH_EHIP;
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return PFSH_EHIP;
+    if (hipEventElapsedTime(&ms, ev[i].first, ev[i].second) != hipSuccess) return PFSH_EHIP;
     sum += ms;
+    ++n;
   }
-  if (launches) *launches = (int)lv->prof[kernel].size();
+  if (launches) *launches = n;
   if (total_ms) *total_ms = sum;
   return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_profile_read(pfsh_level* lv, int kernel, int* launches, double* total_ms) {
+  return pfsh_profile_read_batch(lv, kernel, 0, launches, total_ms);
 }

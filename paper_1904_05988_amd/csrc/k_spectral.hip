@@ -283,7 +283,9 @@ struct SdcMat {
 // One node of the IMEX sweep in Q form (Sec. 4, eq. update), node = 1..M, on
 // [batch][nn][3][K] arrays, fused with the passes that border it:
 //  (a) asm >= 0: F_E at node `asm` from the analysed products Y (assemble_mode);
-//  (b) node == 1: S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j)
+//  (b) node == 1: (optionally first taking node 0 -- state, F_E, F_I -- from
+//      src_*, entry b at src_stride complex values apart, and storing it)
+//      S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j)
 //        - dt sum_{j=1}^{i-1} qE_ij F_E^j - dt sum_{j=1}^{i} qI_ij F_I^j + tau_i
 //      for i = 1..M, every term of the node-i update that uses only the
 //      previous iterate (S_i of i >= 2 kept in S for the later nodes);
@@ -303,7 +305,11 @@ __global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, dou
                                                    void* __restrict__ X,
                                                    const MPInfo* __restrict__ mpi, int T, int CBs,
                                                    int batch, int node, int asm_node, double dt,
-                                                   SdcMat sm, Phys ph) {
+                                                   SdcMat sm, Phys ph,
+                                                   const double* __restrict__ src_th,
+                                                   const double* __restrict__ src_fe,
+                                                   const double* __restrict__ src_fi,
+                                                   long long src_stride) {
   typedef typename Op::R R;
   constexpr int nn = NN, M = NN - 1;
   extern __shared__ unsigned char smem_raw[];
@@ -336,7 +342,18 @@ __global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, dou
             E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
             I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
           }
-          const C2 t0 = ld2(th + 2 * (base + vk));
+          C2 t0;
+          if (src_th) {   // node 0 received from src (state and F there), stored first
+            const size_t so = 2 * ((size_t)b * src_stride + vk);
+            t0 = ld2(src_th + so);
+            E[0] = ld2(src_fe + so);
+            I[0] = ld2(src_fi + so);
+            st2(th + 2 * (base + vk), t0);
+            st2(fe + 2 * (base + vk), E[0]);
+            st2(fi + 2 * (base + vk), I[0]);
+          } else {
+            t0 = ld2(th + 2 * (base + vk));
+          }
 #pragma unroll
           for (int i = 1; i <= M; ++i) {
             double sx = 0, sy = 0;
@@ -772,33 +789,36 @@ hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double
 template <class Op, int NN>
 static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, double dt,
                                   double* th, double* fe, double* fi, const double* tau, int batch,
-                                  hipStream_t s) {
+                                  const StepSrc& src, hipStream_t s) {
   const size_t shm = (size_t)2 * 3 * (lv->T + 1) * sizeof(C2);
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L, (batch + 1) / 2), dim3(256), shm, s, th,
                      fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
-                     lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv));
+                     lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv), src.th, src.fe,
+                     src.fi, src.stride);
   return hipGetLastError();
 }
 
 template <class Op>
 static hipError_t sweep_step_op(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
                                 double* fe, double* fi, const double* tau, int batch,
-                                hipStream_t s) {
-#define PFSH_STEP(NN) return sweep_step_impl<Op, NN>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s)
+                                const StepSrc& src, hipStream_t s) {
+#define PFSH_STEP(NN) \
+  return sweep_step_impl<Op, NN>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s)
   PFSH_NN_SWITCH(lv->nn, PFSH_STEP)
 #undef PFSH_STEP
   return hipSuccess;
 }
 
 hipError_t launch_sweep_step(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
-                             double* fe, double* fi, const double* tau, int batch, hipStream_t s) {
+                             double* fe, double* fi, const double* tau, int batch,
+                             const StepSrc& src, hipStream_t s) {
   switch (lv->op) {
-    case OP_F64: return sweep_step_op<OpF64>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s);
-    case OP_F32: return sweep_step_op<OpF32>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s);
-    default: return sweep_step_op<OpBF3>(lv, node, asm_node, dt, th, fe, fi, tau, batch, s);
+    case OP_F64: return sweep_step_op<OpF64>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s);
+    case OP_F32: return sweep_step_op<OpF32>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s);
+    default: return sweep_step_op<OpBF3>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s);
   }
 }
 

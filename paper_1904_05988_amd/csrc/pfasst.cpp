@@ -77,9 +77,14 @@ Sizes sizes(const pfsh_pfasst* x) {
 }
 
 // F at every node of [batch][nn][3][K] arrays, node by node
+// F at every node of `batch` space-time slices: one RHS call over all
+// batch x nodes states when the level's workspace holds them (the states of a
+// slice's nodes are contiguous), else one call per node.
 hipError_t eval_all(const pfsh_level* lv, double* th, double* fe, double* fi, int batch,
                     hipStream_t s) {
   const long long n3k = 3LL * lv->K, st = lv->nn * n3k;
+  if ((long long)batch * lv->nn <= lv->d.max_batch)
+    return rhs_strided(lv, th, n3k, fe, n3k, fi, n3k, batch * lv->nn, s);
   for (int i = 0; i < lv->nn; ++i)
     PF_TRY(rhs_strided(lv, th + 2 * i * n3k, st, fe + 2 * i * n3k, st, fi + 2 * i * n3k, st, batch, s));
   return hipSuccess;
@@ -106,12 +111,17 @@ hipError_t predict(pfsh_pfasst* x, double dt, const double* th0, double* thf, do
     double* th = x->thc + 2 * (size_t)b0 * z.stc;
     double* fe = x->fec + 2 * (size_t)b0 * z.stc;
     double* fi = x->fic + 2 * (size_t)b0 * z.stc;
+    StepSrc src;
     if (j >= 1) {
       const size_t last = 2 * ((size_t)(b0 - mem) * z.stc + (size_t)Mc * z.n3kc);
-      PF_TRY(launch_copy_node3(x->thc + last, x->fec + last, x->fic + last, z.stc, th, fe, fi,
-                               z.stc, z.n3kc, nb, s));
+      if (Mc >= 2) {   // node 1's kernel takes node 0 (it writes no node >= 2 of any slice)
+        src = StepSrc{x->thc + last, x->fec + last, x->fic + last, z.stc};
+      } else {
+        PF_TRY(launch_copy_node3(x->thc + last, x->fec + last, x->fic + last, z.stc, th, fe, fi,
+                                 z.stc, z.n3kc, nb, s));
+      }
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s));
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, nullptr, nb, s, src));
   }
   // fine prediction and its F at all nodes
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->base, thf, B, s));
@@ -139,12 +149,12 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     double* th = x->thc + o;
     double* fe = x->fec + o;
     double* fi = x->fic + o;
-    if (n >= 1) {   // receive: last-node state of step n-1 and the F there
+    StepSrc src;   // receive: last-node state of step n-1 and the F there
+    if (n >= 1) {
       const size_t last = 2 * ((size_t)(n - 1) * mem * z.stc + (size_t)Mc * z.n3kc);
-      PF_TRY(launch_copy_node3(x->thc + last, x->fec + last, x->fic + last, z.stc, th, fe, fi,
-                               z.stc, z.n3kc, mem, s));
+      src = StepSrc{x->thc + last, x->fec + last, x->fic + last, z.stc};
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s));
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s, src));
   }
   // D) interpolate the coarse increments; new fine initial conditions
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->tthc, thf, B, s));
@@ -205,15 +215,20 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
                           x->tau + oc, nb, s));
     // C) coarse initial conditions (and the F there) from the left neighbours
     //    (super-step t-1), coarse sweeps, send
+    //    (when every step of the range receives, node 1's kernel takes node 0)
     const int r_lo = std::max(b_lo, 1);
+    StepSrc rcv;
     if (r_lo <= b_hi) {
       const int nr = (b_hi - r_lo + 1) * mem;
       const size_t ocr = (size_t)r_lo * mem * fc;
       const double* src = cm_prev + (size_t)(r_lo - 1) * mem * 2 * 3 * z.n3kc;
-      PF_TRY(launch_copy_node3(src, src + 2 * z.n3kc, src + 4 * z.n3kc, 3 * z.n3kc, x->thc + ocr,
-                               x->fec + ocr, x->fic + ocr, z.stc, z.n3kc, nr, s));
+      if (r_lo == b_lo)
+        rcv = StepSrc{src, src + 2 * z.n3kc, src + 4 * z.n3kc, 3 * z.n3kc};
+      else
+        PF_TRY(launch_copy_node3(src, src + 2 * z.n3kc, src + 4 * z.n3kc, 3 * z.n3kc, x->thc + ocr,
+                                 x->fec + ocr, x->fic + ocr, z.stc, z.n3kc, nr, s));
     }
-    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s));
+    PF_TRY(sweep_impl(x->c, dt, x->thc + oc, x->fec + oc, x->fic + oc, x->tau + oc, nb, s, rcv));
     {
       const size_t lastc = oc + 2 * (size_t)Mc * z.n3kc;
       double* dst = cm_now + 3 * omc;

@@ -109,6 +109,7 @@ struct pfsh_level {
   // diagnostic kernel timing (pfsh_profile_*)
   mutable bool prof_on = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[PFSH_K_COUNT];
+  mutable std::vector<int> prof_batch[PFSH_K_COUNT];   // batch of each bracketed launch
 };
 
 namespace pfsh {
@@ -119,8 +120,9 @@ struct ProfScope {
   const pfsh_level* lv;
   int id;
   hipStream_t s;
+  int batch;
   hipEvent_t b = nullptr, e = nullptr;
-  ProfScope(const pfsh_level* l, int k, hipStream_t st) : lv(l), id(k), s(st) {
+  ProfScope(const pfsh_level* l, int k, hipStream_t st, int nb = 0) : lv(l), id(k), s(st), batch(nb) {
     if (!lv->prof_on) return;
     if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) { b = e = nullptr; return; }
     (void)hipEventRecord(b, s);
@@ -129,6 +131,7 @@ struct ProfScope {
     if (!b) return;
     (void)hipEventRecord(e, s);
     lv->prof[id].push_back({b, e});
+    lv->prof_batch[id].push_back(batch);
   }
 };
 
@@ -157,18 +160,29 @@ hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fe_st
                            hipStream_t s);
 hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double* b, double* x,
                                  int batch, hipStream_t s);
+// Node-0 values received from elsewhere (state, F_E, F_I; nullptr = none).
+struct StepSrc {
+  const double* th = nullptr;
+  const double* fe = nullptr;
+  const double* fi = nullptr;
+  long long stride = 0;   // complex values between batch entries
+};
+
 // Compositions of the kernels above (api.cpp): the RHS of strided states; one
-// sweep.
+// sweep (its node 0 optionally received from `src` first).
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s);
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s);
+                      const double* tau, int batch, hipStream_t s,
+                      const StepSrc& src = StepSrc());
 
 // Sweep node `node` (1..M) fused with the F_E assembly of node `asm_node`
-// (-1: none), the old-iterate accumulation (node 1) and the synthesis input of
-// the new node state; leaves the analysis of that state to the caller.
+// (-1: none), the old-iterate accumulation (node 1, optionally taking node 0
+// from `src`) and the synthesis input of the new node state; leaves the
+// analysis of that state to the caller.
 hipError_t launch_sweep_step(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
-                             double* fe, double* fi, const double* tau, int batch, hipStream_t s);
+                             double* fe, double* fi, const double* tau, int batch,
+                             const StepSrc& src, hipStream_t s);
 hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
                            const double* fi, const double* tau, double* out, int batch,
                            hipStream_t s);

@@ -55,6 +55,7 @@ _SIGS = {
     "pfsh_fas_tau": ([_P, _P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_profile_enable": ([_P, _I], _I),
     "pfsh_profile_read": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
+    "pfsh_profile_read_batch": ([_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "pfsh_variant_count": ([_P, _I], _I),
     "pfsh_level_set_variant": ([_P, _I, _I, _I], _I),
     "pfsh_level_get_variant": ([_P, _I, _I, ctypes.POINTER(_I)], _I),
@@ -169,10 +170,13 @@ class Level:
     def profile(self, on=True):
         _check(lib().pfsh_profile_enable(self._h, int(bool(on))), "pfsh_profile_enable")
 
-    def profile_read(self, kernel):
+    def profile_read(self, kernel, batch=0):
+        """(launches, total ms) of a kernel since profile(True); batch > 0 keeps
+        only the launches over that many states."""
         n, ms = ctypes.c_int(), ctypes.c_double()
-        _check(lib().pfsh_profile_read(self._h, self.KERNELS[kernel], ctypes.byref(n),
-                                       ctypes.byref(ms)), "pfsh_profile_read")
+        _check(lib().pfsh_profile_read_batch(self._h, self.KERNELS[kernel], int(batch),
+                                             ctypes.byref(n), ctypes.byref(ms)),
+               "pfsh_profile_read_batch")
         return n.value, ms.value
 
     # -- transform-kernel variants and the autotuner
