@@ -374,7 +374,13 @@ def main():
         work = ring_bytes(Tf, nlf, rsz, B)
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    # HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
+    # counters of this kernel version (reads x2, writes x1 after calibration
+    # against a plain copy): the FP32 ring stage at T255 over 16 slices
+    measured = {("ring", "fp32", 255, 16): 146.94e6}
+    t = measured.get((dom, args.mixed, Tf, B))
+    roof["traffic"] = t                         # HBM bytes per launch (measured)
+    roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
     roof["kernel"] = dom
     roof["launches"] = n
     roof["avg_us"] = avg_s * 1e6
