@@ -239,6 +239,45 @@ def serial_reference(torch, pfsh, inputs, nsweeps=20):
     return np.concatenate(out)       # [step * members + member]
 
 
+def sweep_benchmark(torch, pfsh, inputs, reps=20, rounds=5):
+    """The batched fine sweep alone, per transform precision: 16 independent
+    seeded states (seeds 300..315, spread initial guess) at the fine level,
+    direct launches timed with HIP events (median of `rounds` x `reps` sweeps),
+    and each precision's state after one sweep against the FP64 sweep."""
+    Tf, nlf, nof, nnf = FINE
+    B = 16
+    x0 = torch.from_numpy(inputs.seeded_batch(Tf, range(300, 300 + B), POWER)).to("cuda")
+    out, ref = {}, None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=prec)
+        th, fe, fi = gl.space_time(B), gl.space_time(B), gl.space_time(B)
+        e, i = gl.rhs(x0)
+        th[:, 0] = x0
+        fe[:, 0] = e
+        fi[:, 0] = i
+        gl.spread(th, fe, fi)
+        gl.sdc_sweep(DT, th, fe, fi)
+        one = th[:, -1].cpu().numpy()
+        if ref is None:
+            ref = one
+        times = []
+        for _ in range(rounds):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                gl.sdc_sweep(DT, th, fe, fi)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b) / reps)
+        ms = float(np.median(times))
+        sht = 4 * rhs_sht_flops(Tf, nlf, nof, B)
+        out[prec] = {"ms": ms, "sweeps_per_s": 1e3 / ms, "slice_sweeps_per_s": B * 1e3 / ms,
+                     "sht_tflops": sht / (ms * 1e-3) / 1e12,
+                     "rel_err_vs_fp64_one_sweep": rel_err_slices(one, ref)}
+        gl.close()
+    return out
+
+
 def rel_err_slices(a, b):
     """The paper's normalized max-norm error per variable, each slice (time
     step, member) normalized by its own reference; the maximum over slices."""
@@ -355,6 +394,7 @@ def main():
     err_iter = [rel_err_slices(a, b) for a, b in zip(smx, s64)]
     err_iter_pure = [rel_err_slices(a, b) for a, b in zip(spure, s64)]
     xref = serial_reference(torch, pfsh, inputs)
+    sweeps = sweep_benchmark(torch, pfsh, inputs)
 
     # dominant kernel of the mixed-precision fine level and its roofline
     prof = rpr["prof"]
@@ -412,6 +452,7 @@ def main():
             "fp64": rel_err_slices(x64, xref), "mixed": rel_err_slices(xmx, xref),
             "mixed_without_fp64_iterations": rel_err_slices(xpure, xref)},
         "sweep_only_ms": rmx["sweep_ms"],
+        "sweep_benchmark": sweeps,
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
         "tuned_variants": rmx["tuned"],
