@@ -214,7 +214,12 @@ pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, in
  *            degrees x 64 columns per workgroup, 1 = 64 x 32 with one degree
  *            block per wave (FP64 / FP32: (4,0) (2,0) (8,0) (4,1) (8,1);
  *            BF16x3: (2,0) (4,0) (2,1) (4,1));
- *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4.
+ *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4;
+ *   stage 3, sweep path for batches of 1-2 slices on FP64 / FP32 levels:
+ *            0 = one fused kernel per node and order (Legendre analysis of the
+ *            previous node's products, F_E assembly, node update, Legendre
+ *            synthesis) plus the ring stage, 1 = the separate kernels.  Same
+ *            bits either way; not timed by the tuner.
  * The Legendre variants give bitwise identical results (same order of every
  * sum); the ring variants differ in FFT round-off only.
  * pfsh_level_autotune times every variant of the three stages at `batch`
@@ -225,12 +230,12 @@ pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, in
  * It synchronizes the stream, overwrites the level's workspace (which holds
  * nothing between calls), and returns PFSH_EUNSUPPORTED while the stream is
  * being captured; graphs captured earlier keep the variants they recorded.
- * us_out (host, nullable) receives the best microseconds per launch at
- * [stage * PFSH_MAX_VARIANTS + variant].  One level must not be tuned and
+ * us_out (host, nullable, 3 * PFSH_MAX_VARIANTS floats) receives the best
+ * microseconds per launch at [stage * PFSH_MAX_VARIANTS + variant], stages 0-2.  One level must not be tuned and
  * used on two streams at once.
  * ------------------------------------------------------------------------- */
 #define PFSH_MAX_VARIANTS 8
-/* number of variants of a stage (0..2) on this level, or a negative status */
+/* number of variants of a stage (0..3) on this level, or a negative status */
 int pfsh_variant_count(const pfsh_level* level, int stage);
 pfsh_status pfsh_level_set_variant(pfsh_level* level, int stage, int batch, int variant);
 pfsh_status pfsh_level_get_variant(const pfsh_level* level, int stage, int batch, int* variant);

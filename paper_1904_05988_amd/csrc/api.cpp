@@ -72,6 +72,22 @@ hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, d
                       const double* tau, int batch, hipStream_t s, const StepSrc& src) {
   const long long n3k = 3LL * lv->K;
   const long long stride = lv->nn * n3k;
+  if (node_fused_ok(lv, batch)) {
+    // per node: fused kernel (analysis of the previous node's products +
+    // assembly + node update + synthesis), then the ring stage; a last fused
+    // kernel analyses and assembles F_E of node M
+    for (int i = 1; i <= lv->M; ++i) {
+      {
+        ProfScope p(lv, PFSH_K_SWEEP_NODE, s, batch);
+        PFSH_TRY(launch_node_fused(lv, i, i > 1 ? i - 1 : -1, dt, th, fe, fi, tau, batch,
+                                   i == 1 ? src : StepSrc(), s));
+      }
+      ProfScope p(lv, PFSH_K_RING, s, batch);
+      PFSH_TRY(launch_ring_rhs(lv, batch, s));
+    }
+    ProfScope p(lv, PFSH_K_SWEEP_NODE, s, batch);
+    return launch_node_fused(lv, 0, lv->M, dt, th, fe, fi, tau, batch, StepSrc(), s);
+  }
   for (int i = 1; i <= lv->M; ++i) {
     const int asm_node = i > 1 ? i - 1 : -1;
     {

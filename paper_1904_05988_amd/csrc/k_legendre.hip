@@ -20,46 +20,6 @@
 
 namespace pfsh {
 
-// K loop of one wave's 2x2 blocks: A blocks at ta, ta+1 (+astep per k-block),
-// B blocks at tb, tb+1 (+bstep).  Operands are loaded PF k-blocks ahead into a
-// register ring, so the memory latency overlaps PF k-blocks of matrix work.
-template <class Op, int PF>
-__device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void* __restrict__ B,
-                                         long long ta, long long astep, long long tb,
-                                         long long bstep, int nk, bool r1, bool c1, int lane,
-                                         typename Op::C& acc00, typename Op::C& acc01,
-                                         typename Op::C& acc10, typename Op::C& acc11) {
-  typename Op::A a0[PF], a1[PF], b0[PF], b1[PF];
-#pragma unroll
-  for (int s = 0; s < PF; ++s) {
-    const bool ok = s < nk;
-    a0[s] = ok ? Op::load(A, ta + s * astep, lane) : Op::zero();
-    b0[s] = ok ? Op::load(B, tb + s * bstep, lane) : Op::zero();
-    a1[s] = (ok && r1) ? Op::load(A, ta + s * astep + 1, lane) : Op::zero();
-    b1[s] = (ok && c1) ? Op::load(B, tb + s * bstep + 1, lane) : Op::zero();
-  }
-  for (int k0 = 0; k0 < nk; k0 += PF) {
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      const int kb = k0 + s;
-      if (kb < nk) {
-        acc00 = Op::mma(a0[s], b0[s], acc00);
-        if (c1) acc01 = Op::mma(a0[s], b1[s], acc01);
-        if (r1) acc10 = Op::mma(a1[s], b0[s], acc10);
-        if (r1 && c1) acc11 = Op::mma(a1[s], b1[s], acc11);
-        const int kn = kb + PF;
-        if (kn < nk) {
-          a0[s] = Op::load(A, ta + kn * astep, lane);
-          b0[s] = Op::load(B, tb + kn * bstep, lane);
-          if (r1) a1[s] = Op::load(A, ta + kn * astep + 1, lane);
-          if (c1) b1[s] = Op::load(B, tb + kn * bstep + 1, lane);
-        }
-      }
-    }
-  }
-}
-
-
 // Block id -> (work item, column tile), XCD-aware: the hardware deals
 // consecutive block ids to the 8 XCDs in turn, so item i goes to XCD i % 8 and
 // all column tiles of an item run on that XCD back to back, sharing its table

@@ -192,17 +192,11 @@ __global__ void k_unpack_scalar(const R* __restrict__ Y, double* __restrict__ sp
 // F_E from the analysed products (Sec. 2, transform method):
 //   D[X,Y]_n = (1/a) [ i m X_n - ( -n eps_{n+1} Y_{n+1} + (n+1) eps_n Y_{n-1} ) ]
 //   N_zeta = -D[A,B], N_delta = D[B,-A] + n(n+1)/a^2 E_n, N_Phi = -D[C,D]
-// where X_n, Y_n are the weighted P-contractions (degrees to T+1) of one slice,
-// Yb = [5 products][Kx] complex.
-template <typename R>
-__device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, int eoff, int m,
-                                              int n, int T, double a, C2 out[3]) {
+// where X_n, Y_n are the weighted P-contractions (degrees to T+1) of one slice;
+// get(f, n) returns product f at degree n (0 outside m..T+1).
+template <class GetY>
+__device__ __forceinline__ void assemble_core(GetY get, int m, int n, double a, C2 out[3]) {
   const double ia = 1.0 / a;
-  auto get = [&](int f, int nn) -> C2 {
-    if (nn < m || nn > T + 1) return {0.0, 0.0};
-    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + nn - m);
-    return {(double)p[0], (double)p[1]};
-  };
   const double cp = -(double)n * eps_nm(n + 1, m), cm = (double)(n + 1) * eps_nm(n, m);
   // H-weighted parts: hY = cp Y_{n+1} + cm Y_{n-1}
   const C2 An = get(0, n), Bn = get(1, n), Cn = get(2, n), En = get(4, n);
@@ -225,6 +219,18 @@ __device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, 
     out[1].y = 0;
     out[2].y = 0;
   }
+}
+
+// Products of one slice in global memory, Yb = [5 products][Kx] complex.
+template <typename R>
+__device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, int eoff, int m,
+                                              int n, int T, double a, C2 out[3]) {
+  auto get = [&](int f, int nn) -> C2 {
+    if (nn < m || nn > T + 1) return {0.0, 0.0};
+    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + nn - m);
+    return {(double)p[0], (double)p[1]};
+  };
+  assemble_core(get, m, n, a, out);
 }
 
 template <typename R>
@@ -280,22 +286,116 @@ struct SdcMat {
   int nn;
 };
 
-// One node of the IMEX sweep in Q form (Sec. 4, eq. update), node = 1..M, on
-// [batch][nn][3][K] arrays, fused with the passes that border it:
-//  (a) asm >= 0: F_E at node `asm` from the analysed products Y (assemble_mode);
-//  (b) node == 1: (optionally first taking node 0 -- state, F_E, F_I -- from
-//      src_*, entry b at src_stride complex values apart, and storing it)
-//      S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j)
+// Node-0 values received from elsewhere (state, F_E, F_I), as raw pointers.
+struct SrcPtrs {
+  const double* th;
+  const double* fe;
+  const double* fi;
+  long long stride;   // complex values between batch entries
+};
+
+// One node of the IMEX sweep in Q form (Sec. 4, eq. update), node = 1..M, for
+// one mode k = (m, n) of slice b of [batch][nn][3][K] arrays:
+//  node == 1: (optionally first taking node 0 -- state, F_E, F_I -- from src
+//      and storing it) S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j)
 //        - dt sum_{j=1}^{i-1} qE_ij F_E^j - dt sum_{j=1}^{i} qI_ij F_I^j + tau_i
 //      for i = 1..M, every term of the node-i update that uses only the
 //      previous iterate (S_i of i >= 2 kept in S for the later nodes);
-//  (c) b = S_node + dt sum_{j=1}^{node-1} (qE F_E^j + qI F_I^j) (new F), the
-//      implicit solve with beta = dt qI_{node,node}, Theta^node and
-//      F_I^node = L Theta^node;
-//  (d) the synthesis operand of Theta^node (prep_fields), reading the new
+//  then b = S_node + dt sum_{j=1}^{node-1} (qE F_E^j + qI F_I^j) (new F), the
+//  implicit solve with beta = dt qI_{node,node}, Theta^node and
+//  F_I^node = L Theta^node, stored; returns Theta^node.
+template <int NN>
+__device__ __forceinline__ void node_update(double* __restrict__ th, double* __restrict__ fe,
+                                            double* __restrict__ fi, const double* __restrict__ tau,
+                                            double* __restrict__ S, const SrcPtrs& src, int K,
+                                            int b, int k, int n, int node, double dt,
+                                            const SdcMat& sm, const Phys& ph, C2 x[3]) {
+  constexpr int nn = NN, M = NN - 1;
+  const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
+  const double beta = dt * sm.QI[node * nn + node];
+  const size_t base = (size_t)b * nn * 3 * K;
+  C2 rhs[3];
+  for (int v = 0; v < 3; ++v) {
+    const size_t vk = (size_t)v * K + k;
+    C2 r;
+    if (node == 1) {
+      C2 E[NN], I[NN];
+#pragma unroll
+      for (int j = 0; j < nn; ++j) {
+        E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
+        I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
+      }
+      C2 t0;
+      if (src.th) {   // node 0 received from src (state and F there), stored first
+        const size_t so = 2 * ((size_t)b * src.stride + vk);
+        t0 = ld2(src.th + so);
+        E[0] = ld2(src.fe + so);
+        I[0] = ld2(src.fi + so);
+        st2(th + 2 * (base + vk), t0);
+        st2(fe + 2 * (base + vk), E[0]);
+        st2(fi + 2 * (base + vk), I[0]);
+      } else {
+        t0 = ld2(th + 2 * (base + vk));
+      }
+#pragma unroll
+      for (int i = 1; i <= M; ++i) {
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int j = 0; j < nn; ++j) {
+          const double c = sm.Q[i * nn + j];
+          sx += c * (E[j].x + I[j].x);
+          sy += c * (E[j].y + I[j].y);
+        }
+#pragma unroll
+        for (int j = 1; j < i; ++j) {
+          sx -= sm.QE[i * nn + j] * E[j].x;
+          sy -= sm.QE[i * nn + j] * E[j].y;
+        }
+#pragma unroll
+        for (int j = 1; j <= i; ++j) {
+          sx -= sm.QI[i * nn + j] * I[j].x;
+          sy -= sm.QI[i * nn + j] * I[j].y;
+        }
+        C2 si = {t0.x + dt * sx, t0.y + dt * sy};
+        if (tau) {
+          const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
+          si.x += tv.x;
+          si.y += tv.y;
+        }
+        if (i == 1)
+          r = si;
+        else
+          st2(S + 2 * (((size_t)b * M + (i - 1)) * 3 * K + vk), si);
+      }
+    } else {
+      r = ld2(S + 2 * (((size_t)b * M + (node - 1)) * 3 * K + vk));
+      for (int j = 1; j < node; ++j) {
+        const size_t o = base + (size_t)j * 3 * K + vk;
+        const C2 e = ld2(fe + 2 * o), f = ld2(fi + 2 * o);
+        const double ce = dt * sm.QE[node * nn + j], ci = dt * sm.QI[node * nn + j];
+        r.x += ce * e.x + ci * f.x;
+        r.y += ce * e.y + ci * f.y;
+      }
+    }
+    rhs[v] = r;
+  }
+  solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], x[0], x[1], x[2]);
+  C2 f[3];
+  linear_mode(lam, ph, x[0], x[1], x[2], f);
+  for (int v = 0; v < 3; ++v) {
+    const size_t o = base + ((size_t)node * 3 + v) * K + k;
+    st2(th + 2 * o, x[v]);
+    st2(fi + 2 * o, f[v]);
+  }
+}
+
+// One sweep node fused with the passes that border it:
+//  (a) asm_node >= 0: F_E at node asm_node from the analysed products Y;
+//  (b) node_update (node 1 also accumulates the old-iterate terms);
+//  (c) the synthesis operand of Theta^node (prep_fields), reading the new
 //      states of this order from LDS.
 // One workgroup of 256 threads per (m, pair of slices): the (slice, degree)
-// pairs of (a)-(c) are spread over all threads, (d) takes one degree per thread.
+// pairs of (a)-(b) are spread over all threads, (c) takes one degree per thread.
 template <class Op, int NN>
 __global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
                                                    double* __restrict__ fi,
@@ -305,108 +405,28 @@ __global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, dou
                                                    void* __restrict__ X,
                                                    const MPInfo* __restrict__ mpi, int T, int CBs,
                                                    int batch, int node, int asm_node, double dt,
-                                                   SdcMat sm, Phys ph,
-                                                   const double* __restrict__ src_th,
-                                                   const double* __restrict__ src_fe,
-                                                   const double* __restrict__ src_fi,
-                                                   long long src_stride) {
+                                                   SdcMat sm, Phys ph, SrcPtrs src) {
   typedef typename Op::R R;
-  constexpr int nn = NN, M = NN - 1;
+  constexpr int nn = NN;
   extern __shared__ unsigned char smem_raw[];
   C2* sh = reinterpret_cast<C2*>(smem_raw);            // [2 slices][3 vars][T+1-m]
   const int m = blockIdx.x, b0 = 2 * blockIdx.y;
   const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
   const int off = spec_off(T, m), eoff = ext_off(T, m), nm = T + 1 - m;
-  const double beta = dt * sm.QI[node * nn + node];
   const int nsl = min(2, batch - b0);                  // slices of this workgroup
   for (int it = threadIdx.x; it < nsl * nm; it += blockDim.x) {
     const int bb = it / nm, n = m + (it - bb * nm);
     const int b = b0 + bb;
     const int k = off + n - m;
-    const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
-    {
+    if (asm_node >= 0) {
+      C2 o[3];
+      assemble_mode(Y + (size_t)b * 5 * Kx * 2, Kx, eoff, m, n, T, ph.a, o);
       const size_t base = (size_t)b * nn * 3 * K;
-      if (asm_node >= 0) {
-        C2 o[3];
-        assemble_mode(Y + (size_t)b * 5 * Kx * 2, Kx, eoff, m, n, T, ph.a, o);
-        for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
-      }
-      C2 rhs[3];
-      for (int v = 0; v < 3; ++v) {
-        const size_t vk = (size_t)v * K + k;
-        C2 r;
-        if (node == 1) {
-          C2 E[NN], I[NN];
-#pragma unroll
-          for (int j = 0; j < nn; ++j) {
-            E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
-            I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
-          }
-          C2 t0;
-          if (src_th) {   // node 0 received from src (state and F there), stored first
-            const size_t so = 2 * ((size_t)b * src_stride + vk);
-            t0 = ld2(src_th + so);
-            E[0] = ld2(src_fe + so);
-            I[0] = ld2(src_fi + so);
-            st2(th + 2 * (base + vk), t0);
-            st2(fe + 2 * (base + vk), E[0]);
-            st2(fi + 2 * (base + vk), I[0]);
-          } else {
-            t0 = ld2(th + 2 * (base + vk));
-          }
-#pragma unroll
-          for (int i = 1; i <= M; ++i) {
-            double sx = 0, sy = 0;
-#pragma unroll
-            for (int j = 0; j < nn; ++j) {
-              const double c = sm.Q[i * nn + j];
-              sx += c * (E[j].x + I[j].x);
-              sy += c * (E[j].y + I[j].y);
-            }
-#pragma unroll
-            for (int j = 1; j < i; ++j) {
-              sx -= sm.QE[i * nn + j] * E[j].x;
-              sy -= sm.QE[i * nn + j] * E[j].y;
-            }
-#pragma unroll
-            for (int j = 1; j <= i; ++j) {
-              sx -= sm.QI[i * nn + j] * I[j].x;
-              sy -= sm.QI[i * nn + j] * I[j].y;
-            }
-            C2 si = {t0.x + dt * sx, t0.y + dt * sy};
-            if (tau) {
-              const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
-              si.x += tv.x;
-              si.y += tv.y;
-            }
-            if (i == 1)
-              r = si;
-            else
-              st2(S + 2 * (((size_t)b * M + (i - 1)) * 3 * K + vk), si);
-          }
-        } else {
-          r = ld2(S + 2 * (((size_t)b * M + (node - 1)) * 3 * K + vk));
-          for (int j = 1; j < node; ++j) {
-            const size_t o = base + (size_t)j * 3 * K + vk;
-            const C2 e = ld2(fe + 2 * o), f = ld2(fi + 2 * o);
-            const double ce = dt * sm.QE[node * nn + j], ci = dt * sm.QI[node * nn + j];
-            r.x += ce * e.x + ci * f.x;
-            r.y += ce * e.y + ci * f.y;
-          }
-        }
-        rhs[v] = r;
-      }
-      C2 x[3];
-      solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], x[0], x[1], x[2]);
-      C2 f[3];
-      linear_mode(lam, ph, x[0], x[1], x[2], f);
-      for (int v = 0; v < 3; ++v) {
-        const size_t o = base + ((size_t)node * 3 + v) * K + k;
-        st2(th + 2 * o, x[v]);
-        st2(fi + 2 * o, f[v]);
-        sh[(bb * 3 + v) * nm + (n - m)] = x[v];
-      }
+      for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
     }
+    C2 x[3];
+    node_update<NN>(th, fe, fi, tau, S, src, K, b, k, n, node, dt, sm, ph, x);
+    for (int v = 0; v < 3; ++v) sh[(bb * 3 + v) * nm + (n - m)] = x[v];
   }
   __syncthreads();
   for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
@@ -425,6 +445,130 @@ __global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, dou
       }
     }
     store_operand<Op>(X, mpi, m, n, CBs, b0, vals);
+  }
+}
+
+// ------------------------------------------------ fused node for small batches
+// With one or two slices the serial coarse chain is bound by kernel latency,
+// so one workgroup takes one order m through every stage but the ring stage:
+//  (1) asm_node >= 0: the Legendre analysis of order m (both parities, all
+//      degrees and columns) into LDS, then F_E at node asm_node;
+//  (2) node >= 1: node_update of every degree, the new states into LDS;
+//  (3) node >= 1: the synthesis operand of order m in LDS, then the Legendre
+//      synthesis of order m (both parities, all rings) into the Fourier
+//      workspace.
+// The contractions use the MFMA fragments and K order of k_leg_anal /
+// k_leg_synth (synthesis from the highest degree down), and every spectral
+// step the expressions of the separate kernels, so the results are the same
+// bits.  FP64 and FP32 transform types.  16 waves per workgroup: the heaviest
+// orders (m near 0) have up to ~2 x (T/32) MFMA blocks per contraction, which
+// then run side by side instead of in rounds of one K chain after another.
+template <class Op, int NN>
+__global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, double* __restrict__ fe,
+                                                   double* __restrict__ fi,
+                                                   const double* __restrict__ tau,
+                                                   double* __restrict__ S,
+                                                   const void* __restrict__ tabA,
+                                                   const void* __restrict__ G,
+                                                   const void* __restrict__ tabS,
+                                                   typename Op::R* __restrict__ F4,
+                                                   const MPInfo* __restrict__ mpi, int T, int J,
+                                                   int Lp, int kb2, int CBa, int RB, int kbmax,
+                                                   int batch, int node, int asm_node, double dt,
+                                                   SdcMat sm, Phys ph, SrcPtrs src) {
+  typedef typename Op::R R;
+  constexpr int nn = NN, PF = 4;
+  const int m = blockIdx.x;
+  const int K = (T + 1) * (T + 2) / 2;
+  const int off = spec_off(T, m), nm = T + 1 - m, nx = T + 2 - m;
+  const int nsl = batch;                               // 1 or 2 slices
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int NW = 16;   // waves
+  extern __shared__ unsigned char smem_raw[];
+  C2* sh = reinterpret_cast<C2*>(smem_raw);                     // [2][3][T+1]
+  R* Yl = reinterpret_cast<R*>(sh + 2 * 3 * (T + 1));          // [20 columns][T+2]
+  R* Xl = Yl + 20 * (T + 2);                                    // [2 parities][kbmax][64]
+  for (int i = threadIdx.x; i < 2 * kbmax * 64; i += blockDim.x) Xl[i] = (R)0;
+
+  if (asm_node >= 0) {
+    // (1) analysis: 16 x 16 blocks (parity, degree block, column block)
+    const int ncols = 10 * nsl, CBn = (ncols + 15) / 16;
+    const MPInfo q0 = mpi[2 * m], q1 = mpi[2 * m + 1];
+    const int ntask = (q0.rbA + q1.rbA) * CBn;
+    for (int t = wave; t < ntask; t += NW) {
+      const int cb = t % CBn, r = t / CBn;
+      const int p = r < q0.rbA ? 0 : 1, rb = p ? r - q0.rbA : r;
+      const MPInfo& q = p ? q1 : q0;
+      typename Op::C acc = {}, d1 = {}, d2 = {}, d3 = {};
+      mma_loop<Op, PF>(tabA, G, q.tabA + rb, (long long)q.rbA,
+                       (long long)(2 * m + p) * kb2 * CBa + cb, (long long)CBa, kb2, false,
+                       false, lane, acc, d1, d2, d3);
+      const int c = cb * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = rb * 16 + Op::row(lane, v);
+        if (i < q.np && c < ncols) Yl[c * nx + p + 2 * i] = (R)acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  for (int it = threadIdx.x; it < nsl * nm; it += blockDim.x) {
+    const int bb = it / nm, n = m + (it - bb * nm);
+    const int k = off + n - m;
+    if (asm_node >= 0) {
+      auto get = [&](int f, int q) -> C2 {
+        if (q < m || q > T + 1) return {0.0, 0.0};
+        const int c = (bb * 5 + f) * 2;
+        return {(double)Yl[c * nx + q - m], (double)Yl[(c + 1) * nx + q - m]};
+      };
+      C2 o[3];
+      assemble_core(get, m, n, ph.a, o);
+      const size_t base = (size_t)bb * nn * 3 * K;
+      for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
+    }
+    if (node >= 1) {
+      C2 x[3];
+      node_update<NN>(th, fe, fi, tau, S, src, K, bb, k, n, node, dt, sm, ph, x);
+      for (int v = 0; v < 3; ++v) sh[(bb * 3 + v) * (T + 1) + (n - m)] = x[v];
+    }
+  }
+  if (node < 1) return;
+  __syncthreads();
+  // (3a) synthesis operand of order m: [parity][k-block][lane = k * 16 + column]
+  for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
+    const int p = (n - m) & 1, i = (n - m) >> 1;
+    R* dst = Xl + ((size_t)p * kbmax + i / Op::KB) * 64 + (i % Op::KB) * 16;
+    for (int bb = 0; bb < nsl; ++bb) {
+      auto get = [&](int v, int q) { return sh[(bb * 3 + v) * (T + 1) + (q - m)]; };
+      C2 v4[4];
+      prep_fields(get, m, n, T, ph, v4);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        dst[bb * 8 + 2 * f] = (R)v4[f].x;
+        dst[bb * 8 + 2 * f + 1] = (R)v4[f].y;
+      }
+    }
+  }
+  __syncthreads();
+  // (3b) synthesis: 16 x 16 blocks (parity, ring block), highest degree first
+  const int ntask = 2 * RB;
+  for (int t = wave; t < ntask; t += NW) {
+    const int p = t / RB, rb = t - p * RB;
+    const MPInfo q = mpi[2 * m + p];
+    if (q.kbS == 0) continue;
+    const long long last = q.kbS - 1;
+    typename Op::C acc = {}, d1 = {}, d2 = {}, d3 = {};
+    mma_loop<Op, PF>(tabS, Xl, q.tabS + rb + last * RB, -(long long)RB,
+                     (long long)p * kbmax + last, -1LL, q.kbS, false, false, lane, acc, d1, d2, d3);
+    const int c = lane & 15;
+    if (c < 8 * nsl) {
+      const int b = c >> 3, f = (c & 7) >> 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = rb * 16 + Op::row(lane, v);
+        if (j < J) F4[((((size_t)b * J + j) * 4 + f) * 2 + p) * Lp * 2 + (size_t)m * 2 + (c & 1)] = (R)acc[v];
+      }
+    }
   }
 }
 
@@ -796,9 +940,48 @@ static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, 
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L, (batch + 1) / 2), dim3(256), shm, s, th,
                      fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
-                     lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv), src.th, src.fe,
-                     src.fi, src.stride);
+                     lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
+                     SrcPtrs{src.th, src.fe, src.fi, src.stride});
   return hipGetLastError();
+}
+
+template <class Op, int NN>
+static hipError_t node_fused_impl(const pfsh_level* lv, int node, int asm_node, double dt,
+                                  double* th, double* fe, double* fi, const double* tau, int batch,
+                                  const StepSrc& src, hipStream_t s) {
+  typedef typename Op::R R;
+  const int kbmax = (npar(lv->T, 0, 0) + Op::KB - 1) / Op::KB;
+  const size_t shm = (size_t)2 * 3 * (lv->T + 1) * sizeof(C2) + (size_t)20 * (lv->T + 2) * sizeof(R) +
+                     (size_t)2 * kbmax * 64 * sizeof(R);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)k_node_fused<Op, NN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_node_fused<Op, NN>), dim3(lv->L), dim3(1024), shm, s, th, fe, fi, tau, lv->S,
+                     lv->tabA, lv->G, lv->tabS, (R*)lv->F4, lv->mp_d, lv->T, lv->J, lv->Lp, lv->kb2,
+                     lv->CBa, lv->RB, kbmax, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
+                     SrcPtrs{src.th, src.fe, src.fi, src.stride});
+  return hipGetLastError();
+}
+
+bool node_fused_ok(const pfsh_level* lv, int batch) {
+  if (batch < 1 || batch > 2 || (lv->op != OP_F64 && lv->op != OP_F32)) return false;
+  const size_t rsz = lv->op == OP_F64 ? 8 : 4;
+  const int kbmax = (npar(lv->T, 0, 0) + 3) / 4;
+  const size_t shm = (size_t)2 * 3 * (lv->T + 1) * 16 + (size_t)20 * (lv->T + 2) * rsz +
+                     (size_t)2 * kbmax * 64 * rsz;
+  return shm <= 160 * 1024 && lv->variant[TS_FUSE][tune_bucket(batch)] == 0;
+}
+
+hipError_t launch_node_fused(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
+                             double* fe, double* fi, const double* tau, int batch,
+                             const StepSrc& src, hipStream_t s) {
+#define PFSH_FUSED(NN)                                                                          \
+  return lv->op == OP_F64                                                                      \
+             ? node_fused_impl<OpF64, NN>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s) \
+             : node_fused_impl<OpF32, NN>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s)
+  PFSH_NN_SWITCH(lv->nn, PFSH_FUSED)
+#undef PFSH_FUSED
+  return hipSuccess;
 }
 
 template <class Op>

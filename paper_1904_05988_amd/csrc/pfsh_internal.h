@@ -63,7 +63,10 @@ __host__ __device__ inline int synth_mc(int op) { return op == OP_F64 ? 4 : 8; }
 // is the built-in default.  Bucket b holds sizes in (2^(b-1), 2^b]; the size is
 // the number of 16-column blocks for the Legendre stages and the batch for
 // the ring stage.
-enum TuneStage { TS_SYNTH = 0, TS_ANAL = 1, TS_RING = 2, TS_COUNT = 3 };
+// A fourth stage, not timed by the tuner, selects the sweep path for batches of
+// one or two slices: 0 = fused per-order node kernel (FP64 / FP32 levels),
+// 1 = separate kernels.
+enum TuneStage { TS_SYNTH = 0, TS_ANAL = 1, TS_RING = 2, TS_TUNED = 3, TS_FUSE = 3, TS_COUNT = 4 };
 constexpr int kTuneBuckets = 13;
 inline int tune_bucket(int n) {
   int b = 0;
@@ -181,6 +184,14 @@ hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, d
 // from `src`) and the synthesis input of the new node state; leaves the
 // analysis of that state to the caller.
 hipError_t launch_sweep_step(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
+                             double* fe, double* fi, const double* tau, int batch,
+                             const StepSrc& src, hipStream_t s);
+// One order per workgroup through analysis (of the preceding ring stage's
+// output, when asm_node >= 0) + F_E assembly + node update + synthesis (when
+// node >= 1); batches of one or two slices, FP64 / FP32 levels
+// (node_fused_ok).
+bool node_fused_ok(const pfsh_level* lv, int batch);
+hipError_t launch_node_fused(const pfsh_level* lv, int node, int asm_node, double dt, double* th,
                              double* fe, double* fi, const double* tau, int batch,
                              const StepSrc& src, hipStream_t s);
 hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,

@@ -10,6 +10,7 @@ int leg_variant_count(int op, int stage);
 int ring_variant_count();
 
 int variant_count(int op, int stage) {
+  if (stage == TS_FUSE) return 2;
   return stage == TS_RING ? ring_variant_count() : leg_variant_count(op, stage);
 }
 }  // namespace pfsh
@@ -20,6 +21,7 @@ namespace {
 
 // the bucket that an RHS evaluation of `batch` states uses in each stage
 int stage_bucket(int stage, int batch) {
+  if (stage == TS_FUSE) return tune_bucket(batch);
   if (stage == TS_SYNTH) return tune_bucket((2 * 4 * batch + 15) / 16);
   if (stage == TS_ANAL) return tune_bucket((2 * 5 * batch + 15) / 16);
   return tune_bucket(batch);
@@ -85,7 +87,7 @@ extern "C" pfsh_status pfsh_level_autotune(pfsh_level* lv, int batch, int reps, 
   // variant replaces the default only if it is at least 3% faster.
   constexpr int kRounds = 3;
   hipError_t err = hipSuccess;
-  for (int stage = 0; stage < TS_COUNT && err == hipSuccess; ++stage) {
+  for (int stage = 0; stage < TS_TUNED && err == hipSuccess; ++stage) {
     unsigned char& slot = lv->variant[stage][stage_bucket(stage, batch)];
     const unsigned char keep = slot;
     const int nv = variant_count(lv->op, stage);

@@ -180,7 +180,8 @@ class Level:
         return n.value, ms.value
 
     # -- transform-kernel variants and the autotuner
-    STAGES = {"synth": 0, "anal": 1, "ring": 2}
+    STAGES = {"synth": 0, "anal": 1, "ring": 2, "fuse": 3}
+    TUNED = ("synth", "anal", "ring")
     MAX_VARIANTS = 8
 
     def variant_count(self, stage):
@@ -207,7 +208,8 @@ class Level:
         _check(lib().pfsh_level_autotune(self._h, int(batch), int(reps), s, us),
                "pfsh_level_autotune")
         out = {}
-        for name, st in self.STAGES.items():
+        for name in self.TUNED:
+            st = self.STAGES[name]
             n = self.variant_count(name)
             out[name] = (self.get_variant(name, batch),
                          [us[st * self.MAX_VARIANTS + v] for v in range(n)])

@@ -64,3 +64,32 @@ def test_autotune_keeps_a_valid_choice_and_results():
         gl.set_variant("anal", B + 1, 0)
     with pytest.raises(pfsh.PfshError):
         gl.set_variant("synth", 1, 99)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 1), (127, 192, 384, 1), (63, 96, 192, 2)])
+def test_fused_small_batch_sweep_is_bitwise_equal(prec, T, nlat, nlon, B):
+    """Batches of one or two slices sweep through the fused per-order node
+    kernel by default; the separate kernels give the same bits, also with tau
+    and a received node 0 (the PFASST coarse chain's case)."""
+    import torch
+    from tests._gpu import to_dev
+    gl = pfsh.Level(T, nlat, nlon, 3, max_batch=B, precision=prec)
+    x = to_dev(seeded(T, range(40, 40 + B)))
+    outs = []
+    for variant in (0, 1):
+        gl.set_variant("fuse", B, variant)
+        th, fe, fi = gl.space_time(B), gl.space_time(B), gl.space_time(B)
+        e, i = gl.rhs(x)
+        th[:, 0] = x
+        fe[:, 0] = e
+        fi[:, 0] = i
+        gl.spread(th, fe, fi)
+        tau = torch.zeros_like(th)
+        tau[:, 1:] = th[:, 1:] * 1e-9
+        gl.sdc_sweep(60.0, th, fe, fi)
+        gl.sdc_sweep(60.0, th, fe, fi, tau=tau)
+        outs.append([t.cpu().numpy() for t in (th, fe, fi)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    gl.set_variant("fuse", B, 0)
