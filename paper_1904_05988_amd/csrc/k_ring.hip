@@ -54,6 +54,23 @@ __host__ __device__ constexpr int nstages(int N, int CAP = 16) {
   while (radix_of(N, s, CAP) != 0) ++s;
   return s;
 }
+// NS (product of the earlier radices) of stage s
+__host__ __device__ constexpr int ns_before(int N, int s, int CAP) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= radix_of(N, i, CAP);
+  return ns;
+}
+// Offset of stage s's twiddle table, laid out [r - 1][k] (r = 1..RAD-1,
+// k = 0..NS-1) with the stages that have NS > 1 back to back, and the total.
+__host__ __device__ constexpr int tw_off(int N, int s, int CAP) {
+  int o = 0;
+  for (int i = 0; i < s; ++i) {
+    const int ns = ns_before(N, i, CAP);
+    if (ns > 1) o += (radix_of(N, i, CAP) - 1) * ns;
+  }
+  return o;
+}
+__host__ __device__ constexpr int tw_total(int N, int CAP) { return tw_off(N, nstages(N, CAP), CAP); }
 
 // e^{SIGN 2 pi i k / 16}
 template <int SIGN, typename R>
@@ -137,13 +154,14 @@ __device__ __forceinline__ cpx<R> cmul_s(cpx<R> a, cpx<R> w) {
 }
 
 // One Stockham stage on NSIG padded signals of length N stored back to back
-// in buf (stride padded_len(N)); tw[t] = e^{2 pi i t / N}.  Element i of a
+// in buf (stride padded_len(N)); twiddles from this stage's LDS table
+// (TWLDS) or from the base table tw[t] = e^{2 pi i t / N}.  Element i of a
 // signal sits at padded(i).  When the RAD inputs j + r NB of a butterfly (and
 // its outputs base + r NS) stay in step with the padding -- NB (NS) a multiple
 // of 16, or an output run of RAD | 16 elements aligned to RAD -- their padded
 // addresses are one base plus r times a constant, so the LDS accesses take
 // immediate offsets instead of per-element index arithmetic.
-template <typename R, int N, int RAD, int NSIG, int NT, int SIGN, int NS>
+template <typename R, int N, int RAD, int NSIG, int NT, int SIGN, int NS, bool TWLDS>
 __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int NB = N / RAD;
   constexpr int TOT = NB * NSIG;
@@ -170,9 +188,15 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
         for (int r = 0; r < RAD; ++r) v[q][r] = b[padded(j + r * NB)];
       }
       if (NS > 1) {
-        const cpx<R>* tk = tw + k * STEP;
+        if constexpr (TWLDS) {   // this stage's table [r - 1][k]: consecutive k, constant offsets
+          const cpx<R>* tk = tw + k;
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) v[q][r] = cmul_s<SIGN>(v[q][r], tk[(r - 1) * k * STEP]);
+          for (int r = 1; r < RAD; ++r) v[q][r] = cmul_s<SIGN>(v[q][r], tk[(r - 1) * NS]);
+        } else {                 // the base table e^{2 pi i t / N}, t = r k STEP
+          const cpx<R>* tk = tw + k * STEP;
+#pragma unroll
+          for (int r = 1; r < RAD; ++r) v[q][r] = cmul_s<SIGN>(v[q][r], tk[(r - 1) * k * STEP]);
+        }
       }
       butterfly<RAD, SIGN>(v[q]);
     }
@@ -198,31 +222,48 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   __syncthreads();
 }
 
-template <typename R, int N, int NSIG, int NT, int SIGN, int CAP = 16, int S = 0, int NS = 1>
-__device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
-  if constexpr (S < nstages(N, CAP)) {
-    constexpr int RAD = radix_of(N, S, CAP);
-    fft_stage<R, N, RAD, NSIG, NT, SIGN, NS>(buf, tw);
-    fft_run<R, N, NSIG, NT, SIGN, CAP, S + 1, NS * RAD>(buf, tw);
-  }
-}
-
-// Twiddles e^{2 pi i t / N}: staged in LDS for FP32, read through the cache
-// from global memory for FP64 (staging them measured slower there: the copy
-// per workgroup and the 16-byte LDS reads cost more than the cached loads).
-template <typename R, int N>
+// Twiddles: for FP32 each workgroup builds the per-stage tables (tw_off
+// layout) in LDS from the base table, so that a stage's threads read
+// consecutive entries; FP64 reads the base table through the cache from global
+// memory (staging measured slower there).
+template <typename R, int N, int CAP>
 struct Twiddles {
   static constexpr bool kLds = sizeof(R) == 4;
-  static constexpr int kLdsElems = kLds ? N : 0;
+  static constexpr int kLdsElems = kLds ? tw_total(N, CAP) : 0;
   __device__ static __forceinline__ const cpx<R>* setup(cpx<R>* lds, const cpx<R>* __restrict__ g) {
     if constexpr (kLds) {
-      for (int i = threadIdx.x; i < N; i += blockDim.x) lds[i] = g[i];
-      return lds;  // the caller's next __syncthreads publishes the table
+      for (int idx = threadIdx.x; idx < kLdsElems; idx += blockDim.x) {
+        int o = 0, nsv = 1;
+        for (int st = 0; st < nstages(N, CAP); ++st) {
+          const int rad = radix_of(N, st, CAP);
+          if (nsv > 1) {
+            const int cnt = (rad - 1) * nsv;
+            if (idx < o + cnt) {
+              const int q = idx - o, r = 1 + q / nsv, k = q - (r - 1) * nsv;
+              lds[idx] = g[r * k * (N / (nsv * rad))];
+              break;
+            }
+            o += cnt;
+          }
+          nsv *= rad;
+        }
+      }
+      return lds;  // the caller's next __syncthreads publishes the tables
     } else {
       return g;
     }
   }
 };
+
+template <typename R, int N, int NSIG, int NT, int SIGN, int CAP = 16, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
+  if constexpr (S < nstages(N, CAP)) {
+    constexpr int RAD = radix_of(N, S, CAP);
+    constexpr bool L = Twiddles<R, N, CAP>::kLds;
+    fft_stage<R, N, RAD, NSIG, NT, SIGN, NS, L>(buf, L ? tw + tw_off(N, S, CAP) : tw);
+    fft_run<R, N, NSIG, NT, SIGN, CAP, S + 1, NS * RAD>(buf, tw);
+  }
+}
 
 // Write one complex value (re, im at columns c, c+1) of degree-parity p of
 // order m for ring j into the analysis data operand.
@@ -275,7 +316,7 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
   cpx<R>* twl = buf + 5 * SP;
   constexpr int NT = 256;
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
-  const cpx<R>* tw = Twiddles<R, N>::setup(twl, twg);
+  const cpx<R>* tw = Twiddles<R, N, CAP>::setup(twl, twg);
   for (int i = tid; i < 4 * SP; i += NT) buf[i] = {(R)0, (R)0};
   __syncthreads();
   const R* src = F4 + ((size_t)b * J + j) * 4 * 2 * Lp * 2;
@@ -328,7 +369,7 @@ __global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __rest
   cpx<R>* twl = buf + 4 * SP;
   constexpr int NT = 256;
   const int j = blockIdx.x, f0 = blockIdx.y * 4, tid = threadIdx.x;
-  const cpx<R>* tw = Twiddles<R, N>::setup(twl, twg);
+  const cpx<R>* tw = Twiddles<R, N, 16>::setup(twl, twg);
   for (int i = tid; i < 4 * SP; i += NT) buf[i] = {(R)0, (R)0};
   __syncthreads();
   for (int i = tid; i < 4 * L; i += NT) {
@@ -365,7 +406,7 @@ __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ gr
   constexpr int NT = 256;
   const int j = blockIdx.x, f0 = blockIdx.y * 4, tid = threadIdx.x;
   const int nlat = 2 * J;
-  const cpx<R>* tw = Twiddles<R, N>::setup(twl, twg);
+  const cpx<R>* tw = Twiddles<R, N, 16>::setup(twl, twg);
   for (int i = tid; i < 4 * N; i += NT) {
     const int fl = i / N, k = i - fl * N, f = f0 + fl;
     cpx<R> z = {(R)0, (R)0};
@@ -396,9 +437,10 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
   typedef typename Op::R R;
   const cpx<R>* tw = reinterpret_cast<const cpx<R>*>(lv->tw_d);
   size_t shm;
-  const size_t twl = (size_t)Twiddles<R, N>::kLdsElems * sizeof(cpx<R>);
+  const size_t twl = (size_t)Twiddles<R, N, 16>::kLdsElems * sizeof(cpx<R>);
   if (kind == 0) {
-    shm = (size_t)5 * padded_len(N) * sizeof(cpx<R>) + twl;
+    shm = (size_t)5 * padded_len(N) * sizeof(cpx<R>) +
+          (size_t)Twiddles<R, N, CAP>::kLdsElems * sizeof(cpx<R>);
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
