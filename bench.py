@@ -113,6 +113,28 @@ def ring_bytes(T, nlat, rsz, batch):
     return (4 + 5) * 2 * L * J * batch * 2 * rsz
 
 
+def sweep_node_bytes(T, nn, B, rsz):
+    """Algorithmic HBM bytes of one fused sweep-node launch, averaged over the
+    nodes 1..M of a sweep: FP64 states of 3 K complex per slice read and written
+    (node 1: Theta^0 and all F to form the old-iterate sums, S_2..S_M written;
+    node i: S_i, F of nodes 1..i-1 and the analysed products of node i-1 read,
+    F_E of node i-1 written), plus Theta^i and F_I^i and the synthesis operand."""
+    M = nn - 1
+    K = (T + 1) * (T + 2) // 2
+    st = 3 * K * 16 * B                                   # one FP64 state array
+    Kx = K + T + 1
+    y = 5 * Kx * 2 * rsz * B                              # analysed products
+    x = 8 * Kx * rsz * B                                  # synthesis operand (4 fields, complex)
+    tot = 0
+    for i in range(1, M + 1):
+        if i == 1:
+            tot += (1 + 2 * nn) * st + (M - 1) * st
+        else:
+            tot += st + 2 * (i - 1) * st + y + st
+        tot += 2 * st + x
+    return tot / M
+
+
 def make_block(args, mixed, n64, pfsh, inputs, torch):
     """Levels, PFASST context, arrays and the block closure for one precision
     recipe: fine transforms in `mixed` (FP64 for its last n64 iterations),
@@ -425,6 +447,24 @@ def main():
     roof["launches"] = n
     roof["avg_us"] = avg_s * 1e6
 
+    # every transform stage of the fine level against its own bound
+    stages = {}
+    for k, (cnt, tot_ms) in prof.items():
+        if cnt == 0:
+            continue
+        sec = tot_ms / cnt * 1e-3
+        if k in ("leg_synth", "leg_anal"):
+            fl = legendre_flops(Tf, nlf, (8 if k == "leg_synth" else 10) * B)
+            stages[k] = {"bound": "mfma", "tflops": fl / sec / 1e12,
+                         "frac": fl / sec / 1e12 / PEAKS[args.mixed], "avg_us": sec * 1e6}
+        elif k == "ring":
+            by = ring_bytes(Tf, nlf, rsz, B)
+            stages[k] = {"bound": "hbm", "gbs": by / sec / 1e9, "frac": by / sec / 1e9 / HBM_PEAK,
+                         "avg_us": sec * 1e6}
+        elif k == "sweep_node":
+            by = sweep_node_bytes(Tf, nnf, B, rsz)
+            stages[k] = {"bound": "hbm", "gbs": by / sec / 1e9, "frac": by / sec / 1e9 / HBM_PEAK,
+                         "avg_us": sec * 1e6}
     sht = block_sht_flops(FINE, COARSE, N_TS, args.n_pf, MEMBERS)
     value = args.n_pf * 1e3 / rmx["ms"]
     out = {
@@ -440,6 +480,7 @@ def main():
                    "step": "one PFASST block: predictor + n_pf iterations, fine residual",
                    "seeds": list(SEEDS), "parallelism": "slices x members as batch, 1 GPU"},
         "roofline": roof,
+        "stage_fractions": stages,
         "fp64": {"sweeps_per_s": args.n_pf * 1e3 / r64["ms"], "ms_per_step": r64["ms"],
                  "sweep_only_ms": r64["sweep_ms"],
                  "sht_tflops": sht / (r64["ms"] * 1e-3) / 1e12},

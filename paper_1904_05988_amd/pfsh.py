@@ -165,7 +165,7 @@ class Level:
 
     # -- diagnostic kernel timing
     KERNELS = {"leg_synth": 0, "ring": 1, "leg_anal": 2, "assemble": 3, "prep": 4,
-               "sweep_node": 5, "sweep_pre": 6}
+               "sweep_node": 5}
 
     def profile(self, on=True):
         _check(lib().pfsh_profile_enable(self._h, int(bool(on))), "pfsh_profile_enable")
