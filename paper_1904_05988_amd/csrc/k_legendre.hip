@@ -31,6 +31,15 @@ __device__ __forceinline__ bool xcd_tile(int nitems, int nct, int& item, int& ct
   return item < nitems;
 }
 
+// The same with `per` sub-tiles per item (ring tile x column tile): all of an
+// item's sub-tiles run on one XCD, back to back.
+__device__ __forceinline__ bool xcd_group(int nitems, int per, int& item, int& sub) {
+  const int L = blockIdx.x, xcd = L & 7, r = L >> 3;
+  sub = r % per;
+  item = (r / per) * 8 + xcd;
+  return item < nitems;
+}
+
 template <typename R, int MC>
 __device__ __forceinline__ void store_run(R* dst, const R* v) {
   if constexpr (sizeof(R) == 4) {
@@ -55,18 +64,20 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
                                                       typename Op::R* __restrict__ F4,
                                                       const MPInfo* __restrict__ mpi,
                                                       const WorkItem* __restrict__ items,
-                                                      int nitems, int nct, int RB, int CBs,
+                                                      int nitems, int ntile, int nct, int RB, int CBs,
                                                       int CBn, int ncols, int nf, int J, int T,
                                                       int Lp) {
   typedef typename Op::R R;
   constexpr int SM = MC + 1;                  // padded m-stride of the LDS tile
   __shared__ R stage[32 * 32 * SM];           // [row][column][m]
-  int item, ct;
-  if (!xcd_tile(nitems, nct, item, ct)) return;
+  int item;
+  int sub;
+  if (!xcd_group(nitems, ntile * nct, item, sub)) return;
+  const int tile = sub / nct, ct = sub - tile * nct;
   const WorkItem it = items[item];
   const int p = it.mp & 1, m0 = it.mp >> 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rb0 = it.tile * 2, cb0 = ct * 2;
+  const int rb0 = tile * 2, cb0 = ct * 2;
   const bool r1 = rb0 + 1 < RB, c1 = cb0 + 1 < CBn;
   const int m = m0 + wave;
   typename Op::C acc[4] = {};
@@ -152,10 +163,11 @@ static inline unsigned xcd_grid(int nitems, int nct) {
 
 template <class Op, int MC, int PF>
 static hipError_t synth_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
-  const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2;
-  hipLaunchKernelGGL((k_leg_synth<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, nct)), dim3(64 * MC),
-                     0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d, lv->itemsS,
-                     lv->nitemsS, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J, lv->T, lv->Lp);
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2, ntile = (lv->RB + 1) / 2;
+  hipLaunchKernelGGL((k_leg_synth<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+                     dim3(64 * MC), 0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d,
+                     lv->itemsS, lv->nitemsS, ntile, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J,
+                     lv->T, lv->Lp);
   return hipGetLastError();
 }
 

@@ -121,10 +121,13 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   // work lists, heaviest first so that the hardware's in-order dispatch
   // balances the triangular per-m work
   std::vector<std::pair<long long, WorkItem>> ws, wa;
+  // synthesis: one entry per (m-chunk, parity); its ring tiles and column tiles
+  // are spread by the kernel (all on one XCD, so the chunk's data operand and
+  // table rows are re-read from that XCD's L2)
   for (int m0 = 0; m0 <= lv->T; m0 += lv->MC)
     for (int p = 0; p < 2; ++p) {
       const long long work = lv->mp[2 * m0 + p].kbS;   // the chunk's longest order
-      for (int t = 0; t < (lv->RB + 1) / 2; ++t) ws.push_back({work, WorkItem{2 * m0 + p, t}});
+      ws.push_back({work, WorkItem{2 * m0 + p, 0}});
     }
   for (int i = 0; i < 2 * lv->L; ++i) {
     const MPInfo& q = lv->mp[i];
