@@ -120,14 +120,69 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
 // SHAPE 1 = 64 degrees x 32 columns with one row block per wave (1x2 blocks),
 // which keeps all four waves busy when there are only one or two column
 // blocks (small batches).
+// BF16x3 B fragment of one 32-ring k-block from the FP32 analysis operand: lane
+// l takes rings 8 (l / 16) + e, e = 0..7, of column l % 16, i.e. four rows of
+// each of two consecutive 16 x 4 blocks (g points at the first block's column,
+// `next` blocks apart), split x = hi + lo with both halves rounded to nearest.
+__device__ __forceinline__ Bf16Pair load_g_bf3(const float* __restrict__ g, long long next) {
+  Bf16Pair r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = g[(e >> 2) * next + (e & 3) * 16];
+    const unsigned short hi = bf16_bits_rne(v);
+    const unsigned short lo = bf16_bits_rne(v - bf16_bits_to_float(hi));
+    r.hi[e] = __builtin_bit_cast(__bf16, hi);
+    r.lo[e] = __builtin_bit_cast(__bf16, lo);
+  }
+  return r;
+}
+
+// K loop of one wave's 2x2 BF16x3 blocks with the B operand converted on load;
+// g0 = this lane's first float (k-block 0, column block cb0).
+template <int PF>
+__device__ __forceinline__ void mma_loop_bf3g(const void* __restrict__ A, const float* __restrict__ G,
+                                              long long ta, long long astep, long long g0,
+                                              long long gstep, long long next, long long gcol,
+                                              int nk, bool r1, bool c1, int lane,
+                                              f4_t& acc00, f4_t& acc01, f4_t& acc10, f4_t& acc11) {
+  Bf16Pair a0[PF], a1[PF], b0[PF], b1[PF];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) {
+    const bool ok = s < nk;
+    a0[s] = ok ? OpBF3::load(A, ta + s * astep, lane) : OpBF3::zero();
+    a1[s] = (ok && r1) ? OpBF3::load(A, ta + s * astep + 1, lane) : OpBF3::zero();
+    b0[s] = ok ? load_g_bf3(G + g0 + s * gstep, next) : OpBF3::zero();
+    b1[s] = (ok && c1) ? load_g_bf3(G + g0 + s * gstep + gcol, next) : OpBF3::zero();
+  }
+  for (int k0 = 0; k0 < nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      const int kb = k0 + s;
+      if (kb < nk) {
+        acc00 = OpBF3::mma(a0[s], b0[s], acc00);
+        if (c1) acc01 = OpBF3::mma(a0[s], b1[s], acc01);
+        if (r1) acc10 = OpBF3::mma(a1[s], b0[s], acc10);
+        if (r1 && c1) acc11 = OpBF3::mma(a1[s], b1[s], acc11);
+        const int kn = kb + PF;
+        if (kn < nk) {
+          a0[s] = OpBF3::load(A, ta + kn * astep, lane);
+          b0[s] = load_g_bf3(G + g0 + kn * gstep, next);
+          if (r1) a1[s] = OpBF3::load(A, ta + kn * astep + 1, lane);
+          if (c1) b1[s] = load_g_bf3(G + g0 + kn * gstep + gcol, next);
+        }
+      }
+    }
+  }
+}
+
 template <class Op, int PF, int SHAPE>
 __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
                                                  const void* __restrict__ G,
                                                  typename Op::R* __restrict__ Y,
                                                  const MPInfo* __restrict__ mpi,
                                                  const WorkItem* __restrict__ items, int nitems,
-                                                 int nct, int kb2, int CBa, int CBn, int ncols,
-                                                 int Kx, int T) {
+                                                 int nct, int kb2, int kb2g, int CBa, int CBn,
+                                                 int ncols, int Kx, int T) {
   int item, ct;
   if (!xcd_tile(nitems, nct, item, ct)) return;
   const WorkItem it = items[item];
@@ -138,8 +193,17 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
   if (rb0 >= q.rbA || cb0 >= CBn) return;
   const bool r1 = SHAPE == 0 && rb0 + 1 < q.rbA, c1 = cb0 + 1 < CBn;
   typename Op::C acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-  mma_loop<Op, PF>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
-                   (long long)CBa, kb2, r1, c1, lane, acc00, acc01, acc10, acc11);
+  if constexpr (Op::KIND == OP_BF16X3) {
+    // data operand in 16 x 4 FP32 blocks [mp][kb2g][CBa]: 32-ring k-block kb of
+    // lane l starts at 4-ring block 8 kb + 2 (l / 16)
+    const long long g0 = (((long long)it.mp * kb2g + 2 * (lane >> 4)) * CBa + cb0) * 64 + (lane & 15);
+    mma_loop_bf3g<PF>(tab, reinterpret_cast<const float*>(G), q.tabA + rb0, (long long)q.rbA, g0,
+                      8LL * CBa * 64, (long long)CBa * 64, 64, kb2, r1, c1, lane, acc00, acc01,
+                      acc10, acc11);
+  } else {
+    mma_loop<Op, PF>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
+                     (long long)CBa, kb2, r1, c1, lane, acc00, acc01, acc10, acc11);
+  }
   const int base = ext_off(T, q.m);
   auto put = [&](const typename Op::C& acc, int rb, int cb) {
     const int c = cb * 16 + (lane & 15);
@@ -176,7 +240,7 @@ static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = SHAPE == 0 ? (CBn + 3) / 4 : (CBn + 1) / 2;
   hipLaunchKernelGGL((k_leg_anal<Op, PF, SHAPE>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s,
                      lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
-                     nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
+                     nct, lv->kb2, lv->kb2g, lv->CBa, CBn, ncols, lv->Kx, lv->T);
   return hipGetLastError();
 }
 

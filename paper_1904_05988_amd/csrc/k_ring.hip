@@ -265,6 +265,17 @@ __device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
   }
 }
 
+// The analysis data operand is kept in 16 x 4 blocks of the transform real
+// type for every precision (BF16x3 splits it into hi/lo when loading).
+template <class Op>
+struct GOp {
+  typedef OpF32 T;
+};
+template <>
+struct GOp<OpF64> {
+  typedef OpF64 T;
+};
+
 // Write one complex value (re, im at columns c, c+1) of degree-parity p of
 // order m for ring j into the analysis data operand.
 template <class Op>
@@ -351,8 +362,8 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
     cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
     cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
     if (m == 0) { gp.y = 0; gm.y = 0; }
-    put_g<Op>(G, kb2, CBa, m, 0, j, c, gp.x, gp.y);
-    put_g<Op>(G, kb2, CBa, m, 1, j, c, gm.x, gm.y);
+    put_g<typename GOp<Op>::T>(G, kb2, CBa, m, 0, j, c, gp.x, gp.y);
+    put_g<typename GOp<Op>::T>(G, kb2, CBa, m, 1, j, c, gm.x, gm.y);
   }
 }
 
@@ -425,8 +436,8 @@ __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ gr
     cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
     cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
     if (m == 0) { gp.y = 0; gm.y = 0; }
-    put_g<Op>(G, kb2, CBa, m, 0, j, 2 * f, gp.x, gp.y);
-    put_g<Op>(G, kb2, CBa, m, 1, j, 2 * f, gm.x, gm.y);
+    put_g<typename GOp<Op>::T>(G, kb2, CBa, m, 0, j, 2 * f, gp.x, gp.y);
+    put_g<typename GOp<Op>::T>(G, kb2, CBa, m, 1, j, 2 * f, gm.x, gm.y);
   }
 }
 
@@ -445,7 +456,7 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
       (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP>), dim3(lv->J, count), dim3(256), shm, s,
-                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->Lp, lv->kb2,
+                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->Lp, lv->kb2g,
                        lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
     shm = (size_t)4 * padded_len(N) * sizeof(cpx<R>) + twl;
@@ -460,7 +471,7 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
       (void)hipFuncSetAttribute((const void*)k_ring_anal<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((k_ring_anal<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
-                       gin, lv->G, lv->w_d, tw, lv->J, lv->L, count, lv->kb2, lv->CBa);
+                       gin, lv->G, lv->w_d, tw, lv->J, lv->L, count, lv->kb2g, lv->CBa);
   }
   return hipGetLastError();
 }

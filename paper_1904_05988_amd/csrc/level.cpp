@@ -97,6 +97,7 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   lv->MC = synth_mc(lv->op);
   lv->RB = lv->Jp / 16;
   lv->kb2 = lv->Jp / lv->KB;
+  lv->kb2g = lv->Jp / 4;
   lv->CBs = (2 * 4 * d->max_batch + 15) / 16;
   lv->CBa = (2 * 5 * d->max_batch + 15) / 16;
 
@@ -172,7 +173,9 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   const int B = d->max_batch;
   const size_t bytesX = (size_t)xS * bb;
   const size_t bytesF4 = (size_t)B * lv->J * 5 * 2 * lv->Lp * 2 * rsz;
-  const size_t bytesG = (size_t)2 * lv->L * lv->kb2 * lv->CBa * bb;
+  // analysis data operand: 16 x 4 blocks of the transform real type for every
+  // precision (BF16x3 splits into hi/lo when it loads its fragments)
+  const size_t bytesG = (size_t)2 * lv->L * lv->kb2g * lv->CBa * 64 * rsz;
   const size_t bytesY = (size_t)B * 5 * lv->Kx * 2 * rsz;
   const size_t bytesS = (size_t)B * lv->M * 3 * lv->K * 16;
   const int rblk = 256;

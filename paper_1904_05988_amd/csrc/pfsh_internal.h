@@ -85,6 +85,7 @@ struct pfsh_level {
   int Lp;                  // m-stride of the Fourier workspace (L rounded up to 8)
   int MC;                  // orders m per synthesis workgroup (4 FP64, 8 otherwise)
   int KB, RB, kb2;         // k-block, synthesis row blocks (Jp/16), analysis k-blocks (Jp/KB)
+  int kb2g;                // k-blocks of the analysis data operand (Jp/4: 16 x 4 blocks)
   int CBs, CBa;            // column blocks of the synthesis / analysis data operands
   std::vector<pfsh::MPInfo> mp;
   std::vector<double> mu_h, w_h;          // full grid, north to south
@@ -102,7 +103,7 @@ struct pfsh_level {
   // workspace
   void* X = nullptr;       // synthesis data operand
   void* F4 = nullptr;      // Fourier coefficients [batch][J][nf][2][L] complex (transform type)
-  void* G = nullptr;       // analysis data operand
+  void* G = nullptr;       // analysis data operand (16 x 4 blocks, transform real type)
   void* Y = nullptr;       // analysis result [batch*5][Kx] complex (transform accumulate type)
   double* S = nullptr;     // sweep pre-accumulation [batch][M][3][K] complex
   double* red = nullptr;   // residual partial maxima
