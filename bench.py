@@ -420,26 +420,36 @@ def main():
 
     # dominant kernel of the mixed-precision fine level and its roofline
     prof = rpr["prof"]
-    dom = max(prof, key=lambda k: prof[k][1])
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
     B = N_TS * MEMBERS
+    rsz = 8 if args.mixed == "fp64" else 4
+
+    def kernel_work(k):
+        """(bound, algorithmic work per launch at batch B) of a fine-level kernel"""
+        if k in ("leg_synth", "leg_anal"):
+            return "mfma", legendre_flops(Tf, nlf, (8 if k == "leg_synth" else 10) * B)
+        if k == "ring":
+            return "hbm", ring_bytes(Tf, nlf, rsz, B)
+        if k == "sweep_node":
+            return "hbm", sweep_node_bytes(Tf, nnf, B, rsz)
+        return None, None
+
+    # the dominant kernel among those with a work model
+    dom = max((k for k in prof if kernel_work(k)[0]), key=lambda k: prof[k][1])
     n, tot = prof[dom]
     avg_s = tot / max(n, 1) * 1e-3
-    rsz = 8 if args.mixed == "fp64" else 4
-    if dom in ("leg_synth", "leg_anal"):
-        ncols = (8 if dom == "leg_synth" else 10) * B
-        work = legendre_flops(Tf, nlf, ncols)
+    bound, work = kernel_work(dom)
+    if bound == "mfma":
         roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAKS[args.mixed],
                 "unit": "TFLOP/s"}
     else:
-        work = ring_bytes(Tf, nlf, rsz, B)
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     # HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
     # counters of this kernel version (reads x2, writes x1 after calibration
     # against a plain copy): the FP32 ring stage at T255 over 16 slices
-    measured = {("ring", "fp32", 255, 16): 146.94e6}
+    measured = {}
     t = measured.get((dom, args.mixed, Tf, B))
     roof["traffic"] = t                         # HBM bytes per launch (measured)
     roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
@@ -450,20 +460,15 @@ def main():
     # every transform stage of the fine level against its own bound
     stages = {}
     for k, (cnt, tot_ms) in prof.items():
-        if cnt == 0:
+        bnd, w = kernel_work(k)
+        if cnt == 0 or bnd is None:
             continue
         sec = tot_ms / cnt * 1e-3
-        if k in ("leg_synth", "leg_anal"):
-            fl = legendre_flops(Tf, nlf, (8 if k == "leg_synth" else 10) * B)
-            stages[k] = {"bound": "mfma", "tflops": fl / sec / 1e12,
-                         "frac": fl / sec / 1e12 / PEAKS[args.mixed], "avg_us": sec * 1e6}
-        elif k == "ring":
-            by = ring_bytes(Tf, nlf, rsz, B)
-            stages[k] = {"bound": "hbm", "gbs": by / sec / 1e9, "frac": by / sec / 1e9 / HBM_PEAK,
-                         "avg_us": sec * 1e6}
-        elif k == "sweep_node":
-            by = sweep_node_bytes(Tf, nnf, B, rsz)
-            stages[k] = {"bound": "hbm", "gbs": by / sec / 1e9, "frac": by / sec / 1e9 / HBM_PEAK,
+        if bnd == "mfma":
+            stages[k] = {"bound": "mfma", "tflops": w / sec / 1e12,
+                         "frac": w / sec / 1e12 / PEAKS[args.mixed], "avg_us": sec * 1e6}
+        else:
+            stages[k] = {"bound": "hbm", "gbs": w / sec / 1e9, "frac": w / sec / 1e9 / HBM_PEAK,
                          "avg_us": sec * 1e6}
     sht = block_sht_flops(FINE, COARSE, N_TS, args.n_pf, MEMBERS)
     value = args.n_pf * 1e3 / rmx["ms"]

@@ -20,8 +20,11 @@
 
 namespace pfsh {
 
+// Aligned to its full size, so that an LDS access of one complex is a single
+// 64-bit (FP32) or 128-bit (FP64) access: a pair of 32-bit (64-bit) accesses
+// with stride-2 lanes would reach only half of the banks per pass.
 template <typename R>
-struct cpx {
+struct alignas(2 * sizeof(R)) cpx {
   R x, y;
 };
 template <typename R>
@@ -153,6 +156,25 @@ __device__ __forceinline__ cpx<R> cmul_s(cpx<R> a, cpx<R> w) {
   else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
 }
 
+// Twiddle factors of butterfly k (k = j mod NS) of a stage with NS > 1, from
+// this stage's LDS table [r - 1][k] (TWLDS: consecutive k, constant offsets)
+// or from the base table e^{2 pi i t / N}, t = r k N / (NS RAD).
+template <typename R, int N, int RAD, int SIGN, int NS, bool TWLDS>
+__device__ __forceinline__ void stage_twiddles(cpx<R>* v, const cpx<R>* tw, int k) {
+  if constexpr (NS > 1) {
+    constexpr int STEP = N / (NS * RAD);
+    if constexpr (TWLDS) {
+      const cpx<R>* tk = tw + k;
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) v[r] = cmul_s<SIGN>(v[r], tk[(r - 1) * NS]);
+    } else {
+      const cpx<R>* tk = tw + k * STEP;
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) v[r] = cmul_s<SIGN>(v[r], tk[(r - 1) * k * STEP]);
+    }
+  }
+}
+
 // One Stockham stage on NSIG padded signals of length N stored back to back
 // in buf (stride padded_len(N)); twiddles from this stage's LDS table
 // (TWLDS) or from the base table tw[t] = e^{2 pi i t / N}.  Element i of a
@@ -187,21 +209,13 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
 #pragma unroll
         for (int r = 0; r < RAD; ++r) v[q][r] = b[padded(j + r * NB)];
       }
-      if (NS > 1) {
-        if constexpr (TWLDS) {   // this stage's table [r - 1][k]: consecutive k, constant offsets
-          const cpx<R>* tk = tw + k;
-#pragma unroll
-          for (int r = 1; r < RAD; ++r) v[q][r] = cmul_s<SIGN>(v[q][r], tk[(r - 1) * NS]);
-        } else {                 // the base table e^{2 pi i t / N}, t = r k STEP
-          const cpx<R>* tk = tw + k * STEP;
-#pragma unroll
-          for (int r = 1; r < RAD; ++r) v[q][r] = cmul_s<SIGN>(v[q][r], tk[(r - 1) * k * STEP]);
-        }
-      }
+      stage_twiddles<R, N, RAD, SIGN, NS, TWLDS>(v[q], tw, k);
       butterfly<RAD, SIGN>(v[q]);
     }
   }
-  __syncthreads();
+  // The last stage (NB = NS) writes each butterfly's outputs where its inputs
+  // were, in the same thread, so it needs no barrier between reads and writes.
+  if constexpr (NB != NS) __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = threadIdx.x + q * NT;
@@ -230,24 +244,24 @@ template <typename R, int N, int CAP>
 struct Twiddles {
   static constexpr bool kLds = sizeof(R) == 4;
   static constexpr int kLdsElems = kLds ? tw_total(N, CAP) : 0;
-  __device__ static __forceinline__ const cpx<R>* setup(cpx<R>* lds, const cpx<R>* __restrict__ g) {
-    if constexpr (kLds) {
-      for (int idx = threadIdx.x; idx < kLdsElems; idx += blockDim.x) {
-        int o = 0, nsv = 1;
-        for (int st = 0; st < nstages(N, CAP); ++st) {
-          const int rad = radix_of(N, st, CAP);
-          if (nsv > 1) {
-            const int cnt = (rad - 1) * nsv;
-            if (idx < o + cnt) {
-              const int q = idx - o, r = 1 + q / nsv, k = q - (r - 1) * nsv;
-              lds[idx] = g[r * k * (N / (nsv * rad))];
-              break;
-            }
-            o += cnt;
-          }
-          nsv *= rad;
+  // stage S's table: entry (r - 1) NS + k = e^{2 pi i r k STEP / N}, STEP = N / (NS RAD)
+  template <int S = 0, int NS = 1>
+  __device__ static __forceinline__ void fill(cpx<R>* lds, const cpx<R>* __restrict__ g) {
+    if constexpr (S < nstages(N, CAP)) {
+      constexpr int RAD = radix_of(N, S, CAP);
+      if constexpr (NS > 1) {
+        constexpr int off = tw_off(N, S, CAP), cnt = (RAD - 1) * NS, STEP = N / (NS * RAD);
+        for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+          const int r = 1 + q / NS, kk = q - (r - 1) * NS;
+          lds[off + q] = g[r * kk * STEP];
         }
       }
+      fill<S + 1, NS * RAD>(lds, g);
+    }
+  }
+  __device__ static __forceinline__ const cpx<R>* setup(cpx<R>* lds, const cpx<R>* __restrict__ g) {
+    if constexpr (kLds) {
+      fill(lds, g);
       return lds;  // the caller's next __syncthreads publishes the tables
     } else {
       return g;
@@ -255,13 +269,15 @@ struct Twiddles {
   }
 };
 
-template <typename R, int N, int NSIG, int NT, int SIGN, int CAP = 16, int S = 0, int NS = 1>
+// stages S .. SEND - 1 (SEND < 0: all)
+template <typename R, int N, int NSIG, int NT, int SIGN, int CAP = 16, int SEND = -1, int S = 0,
+          int NS = 1>
 __device__ __forceinline__ void fft_run(cpx<R>* buf, const cpx<R>* tw) {
-  if constexpr (S < nstages(N, CAP)) {
+  if constexpr (S < (SEND < 0 ? nstages(N, CAP) : SEND)) {
     constexpr int RAD = radix_of(N, S, CAP);
     constexpr bool L = Twiddles<R, N, CAP>::kLds;
     fft_stage<R, N, RAD, NSIG, NT, SIGN, NS, L>(buf, L ? tw + tw_off(N, S, CAP) : tw);
-    fft_run<R, N, NSIG, NT, SIGN, CAP, S + 1, NS * RAD>(buf, tw);
+    fft_run<R, N, NSIG, NT, SIGN, CAP, SEND, S + 1, NS * RAD>(buf, tw);
   }
 }
 
@@ -308,7 +324,7 @@ __device__ __forceinline__ void load_pair(cpx<R>* sig, int N, int m, cpx<R> E, c
 template <typename R>
 __device__ __forceinline__ void split_pair(const cpx<R>* sig, int N, int m, cpx<R>& yn,
                                            cpx<R>& ys) {
-  cpx<R> z = sig[padded(m)], w = sig[padded((N - m) % N)];
+  cpx<R> z = sig[padded(m)], w = sig[padded(m ? N - m : 0)];
   yn = {(R)0.5 * (z.x + w.x), (R)0.5 * (z.y - w.y)};
   ys = {(R)0.5 * (z.y + w.y), (R)0.5 * (w.x - z.x)};
 }
@@ -328,42 +344,80 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
   constexpr int NT = 256;
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const cpx<R>* tw = Twiddles<R, N, CAP>::setup(twl, twg);
-  for (int i = tid; i < 4 * SP; i += NT) buf[i] = {(R)0, (R)0};
-  __syncthreads();
-  const R* src = F4 + ((size_t)b * J + j) * 4 * 2 * Lp * 2;
-  for (int i = tid; i < 4 * L; i += NT) {
-    const int f = i / L, m = i - f * L;
-    const R* e = src + ((f * 2 + 0) * Lp + m) * 2;
-    const R* o = src + ((f * 2 + 1) * Lp + m) * 2;
-    load_pair<R>(buf + f * SP, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
+  // orders L .. N - L carry no coefficient; the loads below fill the others
+  for (int t = L + tid; t <= N - L; t += NT) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) buf[f * SP + padded(t)] = {(R)0, (R)0};
+  }
+  const cpx<R>* src = reinterpret_cast<const cpx<R>*>(F4) + ((size_t)b * J + j) * 4 * 2 * Lp;
+  for (int m = tid; m < L; m += NT) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      load_pair<R>(buf + f * SP, N, m, src[(f * 2 + 0) * Lp + m], src[(f * 2 + 1) * Lp + m]);
   }
   __syncthreads();
-  fft_run<R, N, 4, NT, +1, CAP>(buf, tw);
   const double muj = mu[j];
   const R fn = (R)(two_omega * muj), fs = -fn;
-  for (int k = tid; k < N; k += NT) {
-    const int pk = padded(k);
-    const cpx<R> ph = buf[pk], ze = buf[SP + pk], u = buf[2 * SP + pk], v = buf[3 * SP + pk];
+  // grid products at one point k of the four fields (north in x, south in y)
+  auto products = [&](int pk, cpx<R> ph, cpx<R> ze, cpx<R> u, cpx<R> v) {
     const R en = ze.x + fn, es = ze.y + fs;
     buf[pk] = {en * u.x, es * u.y};
     buf[SP + pk] = {en * v.x, es * v.y};
     buf[2 * SP + pk] = {ph.x * u.x, ph.y * u.y};
     buf[3 * SP + pk] = {ph.x * v.x, ph.y * v.y};
     buf[4 * SP + pk] = {(R)0.5 * (u.x * u.x + v.x * v.x), (R)0.5 * (u.y * u.y + v.y * v.y)};
+  };
+  constexpr int SL = nstages(N, CAP) - 1;                 // last stage: NB = NS = N / RAD
+  constexpr int RL = radix_of(N, SL, CAP), NBL = N / RL;
+  if constexpr (NBL % NT == 0 && NBL % 16 == 0) {
+    // The last inverse stage and the products in one pass: a thread owns
+    // butterfly j of all four signals, whose outputs j + r NB are the points
+    // it read, so nothing else touches them before the next barrier.
+    fft_run<R, N, 4, NT, +1, CAP, SL>(buf, tw);
+    constexpr bool TL = Twiddles<R, N, CAP>::kLds;
+    const cpx<R>* twl_last = TL ? tw + tw_off(N, SL, CAP) : tw;
+    for (int jb = tid; jb < NBL; jb += NT) {
+      cpx<R> v[4][RL];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const cpx<R>* pj = buf + f * SP + padded(jb);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) v[f][r] = pj[r * padded_len(NBL)];
+        stage_twiddles<R, N, RL, +1, NBL, TL>(v[f], twl_last, jb);
+        butterfly<RL, +1>(v[f]);
+      }
+#pragma unroll
+      for (int r = 0; r < RL; ++r)
+        products(padded(jb) + r * padded_len(NBL), v[0][r], v[1][r], v[2][r], v[3][r]);
+    }
+  } else {
+    fft_run<R, N, 4, NT, +1, CAP>(buf, tw);
+    for (int k = tid; k < N; k += NT) {
+      const int pk = padded(k);
+      products(pk, buf[pk], buf[SP + pk], buf[2 * SP + pk], buf[3 * SP + pk]);
+    }
   }
   __syncthreads();
   fft_run<R, N, 5, NT, -1, CAP>(buf, tw);
   const R scale = (R)(wq[j] / ((1.0 - muj * muj) * (double)N));
+  // Analysis operand: 16 x 4 blocks [m][parity][j / 4][column / 16] of the
+  // transform real type, ring j % 4 and column % 16 within; field f of state b
+  // is the column pair (re, im) 10 b + 2 f, both in one block and adjacent.
+  // Lanes run over (m, f) with f fastest, so that a store instruction writes
+  // the 40-byte runs of a dozen orders rather than 64 scattered pairs.
+  const size_t pstride = (size_t)kb2 * CBa * 32;   // parity step, in pairs
+  cpx<R>* gj = reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(G) + (size_t)(j >> 2) * CBa * 64 + (j & 3) * 16);
   for (int i = tid; i < 5 * L; i += NT) {
     const int m = i / 5, f = i - m * 5;
     cpx<R> yn, ys;
     split_pair<R>(buf + f * SP, N, m, yn, ys);
-    const int c = (b * 5 + f) * 2;
+    const int c = b * 10 + 2 * f;
+    cpx<R>* g0 = gj + (size_t)m * (2 * pstride) + (((c >> 4) * 64 + (c & 15)) >> 1);
     cpx<R> gp = {(yn.x + ys.x) * scale, (yn.y + ys.y) * scale};
     cpx<R> gm = {(yn.x - ys.x) * scale, (yn.y - ys.y) * scale};
     if (m == 0) { gp.y = 0; gm.y = 0; }
-    put_g<typename GOp<Op>::T>(G, kb2, CBa, m, 0, j, c, gp.x, gp.y);
-    put_g<typename GOp<Op>::T>(G, kb2, CBa, m, 1, j, c, gm.x, gm.y);
+    g0[0] = gp;
+    g0[pstride] = gm;
   }
 }
 
