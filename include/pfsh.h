@@ -208,11 +208,13 @@ pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, in
  * of each transform stage per size bucket (the batch of an RHS evaluation,
  * rounded up to a power of two, after conversion to 16-column MFMA blocks for
  * the Legendre stages); variant 0 is the built-in default.
- *   stage 0, Legendre synthesis: prefetch depth of the K loop
- *            (FP64 / FP32: 4, 2, 8; BF16x3: 2, 4);
+ *   stage 0, Legendre synthesis: prefetch depth of the K loop and wave tile
+ *            (FP64 / FP32: 4, 2, 8 with 32 x 32 per wave; 4, 2 with 64 x 64 per
+ *            wave; 4 with the LDS exchange in two row halves; BF16x3: 2, 4);
  *   stage 1, Legendre analysis: (prefetch depth, tile shape), shape 0 = 64
  *            degrees x 64 columns per workgroup, 1 = 64 x 32 with one degree
- *            block per wave (FP64 / FP32: (4,0) (2,0) (8,0) (4,1) (8,1);
+ *            block per wave, t4 = one wave of 64 x 64 per workgroup
+ *            (FP64 / FP32: (4,0) (2,0) (8,0) (4,1) (8,1) (4,t4) (2,t4);
  *            BF16x3: (2,0) (4,0) (2,1) (4,1));
  *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4;
  *   stage 3, sweep path for batches of 1-2 slices on FP64 / FP32 levels:
@@ -231,8 +233,8 @@ pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, in
  * nothing between calls), and returns PFSH_EUNSUPPORTED while the stream is
  * being captured; graphs captured earlier keep the variants they recorded.
  * us_out (host, nullable, 3 * PFSH_MAX_VARIANTS floats) receives the best
- * microseconds per launch at [stage * PFSH_MAX_VARIANTS + variant], stages 0-2.  One level must not be tuned and
- * used on two streams at once.
+ * microseconds per launch at [stage * PFSH_MAX_VARIANTS + variant], stages
+ * 0-2.  One level must not be tuned and used on two streams at once.
  * ------------------------------------------------------------------------- */
 #define PFSH_MAX_VARIANTS 8
 /* number of variants of a stage (0..3) on this level, or a negative status */

@@ -58,7 +58,7 @@ __device__ __forceinline__ void store_run(R* dst, const R* v) {
 // waves then exchange their tiles through LDS so that every thread stores the
 // MC consecutive-m complex values of one (ring, field) as one contiguous run
 // (64 bytes) in the [slice][ring][field][parity][m] layout the ring stage reads.
-template <class Op, int MC, int PF>
+template <class Op, int MC, int PF, int HS = 32>
 __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ tab,
                                                       const void* __restrict__ X,
                                                       typename Op::R* __restrict__ F4,
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
                                                       int Lp) {
   typedef typename Op::R R;
   constexpr int SM = MC + 1;                  // padded m-stride of the LDS tile
-  __shared__ R stage[32 * 32 * SM];           // [row][column][m]
+  __shared__ R stage[HS * 32 * SM];           // [row][column][m], HS rows per round
   int item;
   int sub;
   if (!xcd_group(nitems, ntile * nct, item, sub)) return;
@@ -90,29 +90,101 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
                      q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, r1, c1, lane, acc[0],
                      acc[1], acc[2], acc[3]);
   }
+  // HS = 32: one exchange of the whole tile; HS = 16: two rounds of one row
+  // block each (half the LDS, so more workgroups fit on a CU)
 #pragma unroll
-  for (int blk = 0; blk < 4; ++blk) {
-    const int rr = (blk >> 1) * 16, cc = (blk & 1) * 16 + (lane & 15);
+  for (int h = 0; h < 32 / HS; ++h) {
+    if (h > 0) __syncthreads();                          // the previous round has been read
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] = (R)acc[blk][v];
-  }
-  __syncthreads();
-  // 32 rows x 16 complex columns, MC complex values each
-  for (int t = threadIdx.x; t < 32 * 16; t += 64 * MC) {
-    const int r = t >> 4, cp = t & 15;
-    const int j = rb0 * 16 + r, c = cb0 * 16 + 2 * cp;
-    if (j >= J || c >= ncols) continue;
-    const int bf = c >> 1, f = bf % nf, b = bf / nf;
-    R out[2 * MC];
-    const R* re = stage + (r * 32 + 2 * cp) * SM;
-    const R* im = re + SM;
+    for (int blk = 0; blk < 4; ++blk) {
+      if (HS == 16 && (blk >> 1) != h) continue;
+      const int rr = HS == 16 ? 0 : (blk >> 1) * 16, cc = (blk & 1) * 16 + (lane & 15);
 #pragma unroll
-    for (int mi = 0; mi < MC; ++mi) {
-      out[2 * mi] = re[mi];
-      out[2 * mi + 1] = im[mi];
+      for (int v = 0; v < 4; ++v)
+        stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] = (R)acc[blk][v];
     }
-    store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
+    __syncthreads();
+    // HS rows x 16 complex columns, MC complex values each
+    for (int t = threadIdx.x; t < HS * 16; t += 64 * MC) {
+      const int r = t >> 4, cp = t & 15;
+      const int j = rb0 * 16 + h * HS + r, c = cb0 * 16 + 2 * cp;
+      if (j >= J || c >= ncols) continue;
+      const int bf = c >> 1, f = bf % nf, b = bf / nf;
+      R out[2 * MC];
+      const R* re = stage + (r * 32 + 2 * cp) * SM;
+      const R* im = re + SM;
+#pragma unroll
+      for (int mi = 0; mi < MC; ++mi) {
+        out[2 * mi] = re[mi];
+        out[2 * mi + 1] = im[mi];
+      }
+      store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
+    }
+  }
+}
+
+// The same with a 64-ring x 64-column tile per wave (4x4 MFMA blocks: the
+// table and the data operand are each read half as often).  The LDS exchange
+// runs in four rounds of one 32 x 32 quadrant, so it needs no more LDS.
+template <class Op, int MC, int PF>
+__global__ __launch_bounds__(64 * MC) void k_leg_synth_t4(const void* __restrict__ tab,
+                                                         const void* __restrict__ X,
+                                                         typename Op::R* __restrict__ F4,
+                                                         const MPInfo* __restrict__ mpi,
+                                                         const WorkItem* __restrict__ items,
+                                                         int nitems, int ntile, int nct, int RB,
+                                                         int CBs, int CBn, int ncols, int nf, int J,
+                                                         int T, int Lp) {
+  typedef typename Op::R R;
+  constexpr int SM = MC + 1;
+  __shared__ R stage[32 * 32 * SM];
+  int item;
+  int sub;
+  if (!xcd_group(nitems, ntile * nct, item, sub)) return;
+  const int tile = sub / nct, ct = sub - tile * nct;
+  const WorkItem it = items[item];
+  const int p = it.mp & 1, m0 = it.mp >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb0 = tile * 4, cb0 = ct * 4;
+  const int nr = min(4, RB - rb0), nc = min(4, CBn - cb0);
+  const int m = m0 + wave;
+  typename Op::C acc[4][4] = {};
+  if (m <= T) {
+    const MPInfo q = mpi[2 * m + p];
+    const long long last = q.kbS - 1;
+    mma_tile<Op, PF, 4, 4>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
+                           q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, nr, nc, lane, acc);
+  }
+#pragma unroll
+  for (int qd = 0; qd < 4; ++qd) {
+    const int qr = qd >> 1, qc = qd & 1;
+    if (2 * qr >= nr || 2 * qc >= nc) continue;          // uniform over the workgroup
+    if (qd > 0) __syncthreads();                          // the previous round has been read
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const int rr = (blk >> 1) * 16, cc = (blk & 1) * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] =
+            (R)acc[2 * qr + (blk >> 1)][2 * qc + (blk & 1)][v];
+    }
+    __syncthreads();
+    const int rq = (rb0 + 2 * qr) * 16, cq = (cb0 + 2 * qc) * 16;
+    for (int t = threadIdx.x; t < 32 * 16; t += 64 * MC) {
+      const int r = t >> 4, cp = t & 15;
+      const int j = rq + r, c = cq + 2 * cp;
+      if (j >= J || c >= ncols) continue;
+      const int bf = c >> 1, f = bf % nf, b = bf / nf;
+      R out[2 * MC];
+      const R* re = stage + (r * 32 + 2 * cp) * SM;
+      const R* im = re + SM;
+#pragma unroll
+      for (int mi = 0; mi < MC; ++mi) {
+        out[2 * mi] = re[mi];
+        out[2 * mi + 1] = im[mi];
+      }
+      store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
+    }
   }
 }
 
@@ -221,17 +293,75 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
   if (r1 && c1) put(acc11, rb0 + 1, cb0 + 1);
 }
 
+// One wave per workgroup with a 64-degree x 64-column tile (4x4 MFMA blocks):
+// the table rows of a degree tile are read once per 64 columns, the data
+// operand once per degree tile.
+template <class Op, int PF>
+__global__ __launch_bounds__(64) void k_leg_anal_t4(const void* __restrict__ tab,
+                                                   const void* __restrict__ G,
+                                                   typename Op::R* __restrict__ Y,
+                                                   const MPInfo* __restrict__ mpi,
+                                                   const WorkItem* __restrict__ items, int nitems,
+                                                   int nct, int kb2, int CBa, int CBn, int ncols,
+                                                   int Kx, int T) {
+  int item, ct;
+  if (!xcd_tile(nitems, nct, item, ct)) return;
+  const WorkItem it = items[item];
+  const MPInfo q = mpi[it.mp];
+  const int lane = threadIdx.x;
+  const int rb0 = it.tile * 4, cb0 = ct * 4;
+  const int nr = min(4, q.rbA - rb0), nc = min(4, CBn - cb0);
+  if (nr <= 0 || nc <= 0) return;
+  typename Op::C acc[4][4] = {};
+  mma_tile<Op, PF, 4, 4>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
+                         (long long)CBa, kb2, nr, nc, lane, acc);
+  const int base = ext_off(T, q.m);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (r >= nr || cb >= nc) continue;
+      const int c = (cb0 + cb) * 16 + (lane & 15);
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (rb0 + r) * 16 + Op::row(lane, v);
+        if (i < q.np)
+          Y[((size_t)(c >> 1) * Kx + base + q.p + 2 * i) * 2 + (c & 1)] = (typename Op::R)acc[r][cb][v];
+      }
+    }
+}
+
 static inline unsigned xcd_grid(int nitems, int nct) {
   return (unsigned)(((nitems + 7) / 8) * 8 * nct);
 }
 
-template <class Op, int MC, int PF>
+template <class Op, int MC, int PF, int HS = 32>
 static hipError_t synth_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2, ntile = (lv->RB + 1) / 2;
-  hipLaunchKernelGGL((k_leg_synth<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+  hipLaunchKernelGGL((k_leg_synth<Op, MC, PF, HS>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
                      dim3(64 * MC), 0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d,
                      lv->itemsS, lv->nitemsS, ntile, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J,
                      lv->T, lv->Lp);
+  return hipGetLastError();
+}
+
+template <class Op, int MC, int PF>
+static hipError_t synth_t4_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4, ntile = (lv->RB + 3) / 4;
+  hipLaunchKernelGGL((k_leg_synth_t4<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+                     dim3(64 * MC), 0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d,
+                     lv->itemsS, lv->nitemsS, ntile, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J,
+                     lv->T, lv->Lp);
+  return hipGetLastError();
+}
+
+template <class Op, int PF>
+static hipError_t anal_t4_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
+  hipLaunchKernelGGL((k_leg_anal_t4<Op, PF>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(64), 0, s,
+                     lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
+                     nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
   return hipGetLastError();
 }
 
@@ -245,13 +375,15 @@ static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
 }
 
 // Variant lists (index 0 = default):
-//   synthesis, prefetch depth of the K loop: FP64 / FP32 4 2 8; BF16x3 2 4
+//   synthesis, prefetch depth of the K loop (t4: 4x4-block wave tiles):
+//     FP64 / FP32 4 2 8 t4-4 t4-2 4h (4h: LDS exchange in two row halves);
+//     BF16x3 2 4
 //   analysis, (prefetch depth, tile shape): FP64 / FP32 (4,0) (2,0) (8,0) (4,1)
-//     (8,1); BF16x3 (2,0) (4,0) (2,1) (4,1)
-// Neither changes the order of any sum, so all variants give the same bits.
+//     (8,1) (4,t4) (2,t4); BF16x3 (2,0) (4,0) (2,1) (4,1)
+// None changes the order of any sum, so all variants give the same bits.
 int leg_variant_count(int op, int stage) {
-  if (stage == TS_SYNTH) return op == OP_BF16X3 ? 2 : 3;
-  return op == OP_BF16X3 ? 4 : 5;
+  if (stage == TS_SYNTH) return op == OP_BF16X3 ? 2 : 6;
+  return op == OP_BF16X3 ? 4 : 7;
 }
 
 hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
@@ -260,10 +392,16 @@ hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t
     case OP_F64:
       return v == 1 ? synth_impl<OpF64, 4, 2>(lv, ncols, nf, s)
            : v == 2 ? synth_impl<OpF64, 4, 8>(lv, ncols, nf, s)
+           : v == 3 ? synth_t4_impl<OpF64, 4, 4>(lv, ncols, nf, s)
+           : v == 4 ? synth_t4_impl<OpF64, 4, 2>(lv, ncols, nf, s)
+           : v == 5 ? synth_impl<OpF64, 4, 4, 16>(lv, ncols, nf, s)
                     : synth_impl<OpF64, 4, 4>(lv, ncols, nf, s);
     case OP_F32:
       return v == 1 ? synth_impl<OpF32, 8, 2>(lv, ncols, nf, s)
            : v == 2 ? synth_impl<OpF32, 8, 8>(lv, ncols, nf, s)
+           : v == 3 ? synth_t4_impl<OpF32, 8, 4>(lv, ncols, nf, s)
+           : v == 4 ? synth_t4_impl<OpF32, 8, 2>(lv, ncols, nf, s)
+           : v == 5 ? synth_impl<OpF32, 8, 4, 16>(lv, ncols, nf, s)
                     : synth_impl<OpF32, 8, 4>(lv, ncols, nf, s);
     default:
       return v == 1 ? synth_impl<OpBF3, 8, 4>(lv, ncols, nf, s)
@@ -286,6 +424,8 @@ static hipError_t anal_variant(const pfsh_level* lv, int v, int ncols, hipStream
       case 2: return anal_impl<Op, 8, 0>(lv, ncols, s);
       case 3: return anal_impl<Op, 4, 1>(lv, ncols, s);
       case 4: return anal_impl<Op, 8, 1>(lv, ncols, s);
+      case 5: return anal_t4_impl<Op, 4>(lv, ncols, s);
+      case 6: return anal_t4_impl<Op, 2>(lv, ncols, s);
       default: return anal_impl<Op, 4, 0>(lv, ncols, s);
     }
   }

@@ -151,5 +151,46 @@ __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void*
   }
 }
 
+// K loop of one wave's RT x CT blocks (rows ta + r, columns tb + c; r < nr,
+// c < nc valid): RT + CT operand loads feed RT CT MFMAs per k-block, so larger
+// tiles re-read the operands fewer times.  Every block accumulates its k-blocks
+// in the same order as mma_loop, so the results are the same bits.
+template <class Op, int PF, int RT, int CT>
+__device__ __forceinline__ void mma_tile(const void* __restrict__ A, const void* __restrict__ B,
+                                         long long ta, long long astep, long long tb,
+                                         long long bstep, int nk, int nr, int nc, int lane,
+                                         typename Op::C (&acc)[RT][CT]) {
+  typename Op::A a[PF][RT], b[PF][CT];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) {
+    const bool ok = s < nk;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[s][r] = (ok && r < nr) ? Op::load(A, ta + s * astep + r, lane) : Op::zero();
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[s][c] = (ok && c < nc) ? Op::load(B, tb + s * bstep + c, lane) : Op::zero();
+  }
+  for (int k0 = 0; k0 < nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      const int kb = k0 + s;
+      if (kb < nk) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            if (r < nr && c < nc) acc[r][c] = Op::mma(a[s][r], b[s][c], acc[r][c]);
+        const int kn = kb + PF;
+        if (kn < nk) {
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            if (r < nr) a[s][r] = Op::load(A, ta + kn * astep + r, lane);
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            if (c < nc) b[s][c] = Op::load(B, tb + kn * bstep + c, lane);
+        }
+      }
+    }
+  }
+}
 
 }  // namespace pfsh
