@@ -394,10 +394,14 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
 //  (b) node_update (node 1 also accumulates the old-iterate terms);
 //  (c) the synthesis operand of Theta^node (prep_fields), reading the new
 //      states of this order from LDS.
-// One workgroup of 256 threads per (m, pair of slices): the (slice, degree)
-// pairs of (a)-(b) are spread over all threads, (c) takes one degree per thread.
+// One workgroup of 256 threads per (pair of orders, pair of slices): order g
+// goes with order T + 1 - g, so that every workgroup holds T + 1 degrees per
+// slice (order 0 and, for even T + 1, order (T + 1) / 2 stand alone).  The
+// (slice, order, degree) items of (a)-(b) are spread over all threads, (c)
+// takes one (order, degree) per thread.
 template <class Op, int NN>
-__global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NN <= 5 ? 4 : 1)))
+void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
                                                    double* __restrict__ fi,
                                                    const double* __restrict__ tau,
                                                    double* __restrict__ S,
@@ -409,33 +413,41 @@ __global__ __launch_bounds__(256) void k_sweep_step(double* __restrict__ th, dou
   typedef typename Op::R R;
   constexpr int nn = NN;
   extern __shared__ unsigned char smem_raw[];
-  C2* sh = reinterpret_cast<C2*>(smem_raw);            // [2 slices][3 vars][T+1-m]
-  const int m = blockIdx.x, b0 = 2 * blockIdx.y;
+  C2* sh = reinterpret_cast<C2*>(smem_raw);            // [2 slices][3 vars][T+1]: order a, then b
+  const int L = T + 1, g = blockIdx.x, b0 = 2 * blockIdx.y;
+  const int ma = g, mb = (g >= 1 && L - g > g) ? L - g : -1;   // mb < 0: no second order
+  const int na = L - ma, nb = mb >= 0 ? L - mb : 0;    // degrees of each order
   const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
-  const int off = spec_off(T, m), eoff = ext_off(T, m), nm = T + 1 - m;
   const int nsl = min(2, batch - b0);                  // slices of this workgroup
-  for (int it = threadIdx.x; it < nsl * nm; it += blockDim.x) {
-    const int bb = it / nm, n = m + (it - bb * nm);
+  const int per = na + nb;
+  for (int it = threadIdx.x; it < nsl * per; it += blockDim.x) {
+    const int bb = it / per, idx = it - bb * per;
+    const bool first = idx < na;
+    const int m = first ? ma : mb, n = m + (first ? idx : idx - na);
     const int b = b0 + bb;
-    const int k = off + n - m;
+    const int k = spec_off(T, m) + n - m;
     if (asm_node >= 0) {
       C2 o[3];
-      assemble_mode(Y + (size_t)b * 5 * Kx * 2, Kx, eoff, m, n, T, ph.a, o);
+      assemble_mode(Y + (size_t)b * 5 * Kx * 2, Kx, ext_off(T, m), m, n, T, ph.a, o);
       const size_t base = (size_t)b * nn * 3 * K;
       for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
     }
     C2 x[3];
     node_update<NN>(th, fe, fi, tau, S, src, K, b, k, n, node, dt, sm, ph, x);
-    for (int v = 0; v < 3; ++v) sh[(bb * 3 + v) * nm + (n - m)] = x[v];
+    for (int v = 0; v < 3; ++v) sh[(bb * 3 + v) * L + idx] = x[v];
   }
   __syncthreads();
-  for (int n = m + threadIdx.x; n <= T + 1; n += blockDim.x) {
+  // degrees m..T+1 of each order (T+1 is the extra degree of the vector terms)
+  for (int t = threadIdx.x; t < (na + 1) + (nb > 0 ? nb + 1 : 0); t += blockDim.x) {
+    const bool first = t <= na;
+    const int m = first ? ma : mb, n = m + (first ? t : t - (na + 1));
+    const int base = first ? 0 : na;                   // this order's LDS offset
     R vals[16];
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       C2 v4[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
       if (b0 + bb < batch) {
-        auto get = [&](int v, int q) { return sh[(bb * 3 + v) * nm + (q - m)]; };
+        auto get = [&](int v, int q) { return sh[(bb * 3 + v) * L + base + (q - m)]; };
         prep_fields(get, m, n, T, ph, v4);
       }
 #pragma unroll
@@ -938,7 +950,8 @@ static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, 
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L, (batch + 1) / 2), dim3(256), shm, s, th,
+  // order pairs (g, L - g): order 0, L/2 - 1 or (L-1)/2 pairs, and order L/2 for even L
+  hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm, s, th,
                      fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
                      lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
                      SrcPtrs{src.th, src.fe, src.fi, src.stride});
