@@ -187,7 +187,8 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
     """K timed PFASST blocks of one precision recipe."""
     ctx = make_block(args, mixed, n64, pfsh, inputs, torch)
     pf, block = ctx["pf"], ctx["block"]
-    gfm = ctx["levels"][0]
+    gfm, gc, gf64 = ctx["levels"]
+    named = [("fine", gfm), ("coarse", gc)] + ([] if gf64 is gfm else [("fine_fp64", gf64)])
     thf, fef, fif = ctx["arrays"]
     stream = torch.cuda.Stream()
     pf.set_graphs(not profile)
@@ -196,17 +197,24 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
             block()
         torch.cuda.synchronize()
         if profile:
-            gfm.profile(True)
+            for _, lv in named:
+                lv.profile(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             block()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = None
+        prof = per_level = None
         if profile:
-            gfm.profile(False)
+            for _, lv in named:
+                lv.profile(False)
             # launches over the B slices (the one-off F at all nodes runs at B x nodes)
             prof = {k: gfm.profile_read(k, batch=N_TS * MEMBERS) for k in gfm.KERNELS}
+            # every launch of every level, ms per block (event-bracketed, no graphs)
+            per_level = {}
+            for name, lv in named:
+                d = {k: lv.profile_read(k) for k in lv.KERNELS}
+                per_level[name] = {k: round(ms / args.steps, 4) for k, (n, ms) in d.items() if n}
         s0 = time.perf_counter()
         for _ in range(10):
             gfm.sdc_sweep(DT, thf, fef, fif)
@@ -214,7 +222,8 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
         sweep_ms = (time.perf_counter() - s0) * 1e3 / 10
     pf.set_graphs(False)
     pf.close()
-    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, sweep_ms=sweep_ms, tuned=ctx["tuned"])
+    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, per_level=per_level, sweep_ms=sweep_ms,
+                tuned=ctx["tuned"])
 
 
 def run_states(args, mixed, n64, torch, pfsh, inputs):
@@ -446,10 +455,11 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    # HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
-    # counters of this kernel version (reads x2, writes x1 after calibration
-    # against a plain copy): the FP32 ring stage at T255 over 16 slices
-    measured = {}
+    # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counters of these kernel
+    # versions (reads x2, writes x1 after calibration against a plain copy), FP32
+    # fine level at T255 over 16 slices; the sweep node is averaged over nodes 1-4
+    measured = {("sweep_node", "fp32", 255, 16): 297.27e6, ("ring", "fp32", 255, 16): 144.89e6,
+                ("leg_synth", "fp32", 255, 16): 104.49e6, ("leg_anal", "fp32", 255, 16): 166.46e6}
     t = measured.get((dom, args.mixed, Tf, B))
     roof["traffic"] = t                         # HBM bytes per launch (measured)
     roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
@@ -501,6 +511,7 @@ def main():
         "sweep_benchmark": sweeps,
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
+        "kernel_ms_per_step_all_levels": rpr["per_level"],
         "tuned_variants": rmx["tuned"],
     }
     if not args.no_cpu_baseline:

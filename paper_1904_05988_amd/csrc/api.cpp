@@ -69,10 +69,14 @@ hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstr
 // assembly of each node runs in the next node's kernel, the last one on its
 // own.  src: node 0 (state, F_E, F_I) is taken from there by node 1's kernel.
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
-                      const double* tau, int batch, hipStream_t s, const StepSrc& src) {
+                      const double* tau, int batch, hipStream_t s, const StepSrc& src,
+                      bool defer_last) {
   const long long n3k = 3LL * lv->K;
   const long long stride = lv->nn * n3k;
-  if (node_fused_ok(lv, batch)) {
+  const bool fused = node_fused_ok(lv, batch);
+  if (!fused && (defer_last || src.fe_pending)) return hipErrorInvalidValue;
+  if (src.fe_pending && (src.fe_pending != src.fe || !src.th)) return hipErrorInvalidValue;
+  if (fused) {
     // per node: fused kernel (analysis of the previous node's products +
     // assembly + node update + synthesis), then the ring stage; a last fused
     // kernel analyses and assembles F_E of node M
@@ -85,6 +89,7 @@ hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, d
       ProfScope p(lv, PFSH_K_RING, s, batch);
       PFSH_TRY(launch_ring_rhs(lv, batch, s));
     }
+    if (defer_last) return hipSuccess;
     ProfScope p(lv, PFSH_K_SWEEP_NODE, s, batch);
     return launch_node_fused(lv, 0, lv->M, dt, th, fe, fi, tau, batch, StepSrc(), s);
   }

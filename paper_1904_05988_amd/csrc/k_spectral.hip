@@ -286,12 +286,15 @@ struct SdcMat {
   int nn;
 };
 
-// Node-0 values received from elsewhere (state, F_E, F_I), as raw pointers.
+// Node-0 values received from elsewhere (state, F_E, F_I), as raw pointers;
+// fe_pending (fused node kernel only): F_E there is assembled first, into this
+// array (the same as fe), from the level's current ring output.
 struct SrcPtrs {
   const double* th;
   const double* fe;
   const double* fi;
   long long stride;   // complex values between batch entries
+  double* fe_pending;
 };
 
 // One node of the IMEX sweep in Q form (Sec. 4, eq. update), node = 1..M, for
@@ -502,7 +505,8 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
   R* Xl = Yl + 20 * (T + 2);                                    // [2 parities][kbmax][64]
   for (int i = threadIdx.x; i < 2 * kbmax * 64; i += blockDim.x) Xl[i] = (R)0;
 
-  if (asm_node >= 0) {
+  const bool asm_src = src.fe_pending != nullptr;   // with node 1 only (asm_node < 0)
+  if (asm_node >= 0 || asm_src) {
     // (1) analysis: 16 x 16 blocks (parity, degree block, column block)
     const int ncols = 10 * nsl, CBn = (ncols + 15) / 16;
     const MPInfo q0 = mpi[2 * m], q1 = mpi[2 * m + 1];
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
   for (int it = threadIdx.x; it < nsl * nm; it += blockDim.x) {
     const int bb = it / nm, n = m + (it - bb * nm);
     const int k = off + n - m;
-    if (asm_node >= 0) {
+    if (asm_node >= 0 || asm_src) {
       auto get = [&](int f, int q) -> C2 {
         if (q < m || q > T + 1) return {0.0, 0.0};
         const int c = (bb * 5 + f) * 2;
@@ -535,8 +539,13 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
       };
       C2 o[3];
       assemble_core(get, m, n, ph.a, o);
-      const size_t base = (size_t)bb * nn * 3 * K;
-      for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
+      if (asm_src) {   // the source's F_E, read back by this thread in node_update below
+        for (int v = 0; v < 3; ++v)
+          st2(src.fe_pending + 2 * ((size_t)bb * src.stride + (size_t)v * K + k), o[v]);
+      } else {
+        const size_t base = (size_t)bb * nn * 3 * K;
+        for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
+      }
     }
     if (node >= 1) {
       C2 x[3];
@@ -954,7 +963,7 @@ static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, 
   hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm, s, th,
                      fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
                      lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
-                     SrcPtrs{src.th, src.fe, src.fi, src.stride});
+                     SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});
   return hipGetLastError();
 }
 
@@ -972,7 +981,7 @@ static hipError_t node_fused_impl(const pfsh_level* lv, int node, int asm_node, 
   hipLaunchKernelGGL((k_node_fused<Op, NN>), dim3(lv->L), dim3(1024), shm, s, th, fe, fi, tau, lv->S,
                      lv->tabA, lv->G, lv->tabS, (R*)lv->F4, lv->mp_d, lv->T, lv->J, lv->Lp, lv->kb2,
                      lv->CBa, lv->RB, kbmax, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
-                     SrcPtrs{src.th, src.fe, src.fi, src.stride});
+                     SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});
   return hipGetLastError();
 }
 

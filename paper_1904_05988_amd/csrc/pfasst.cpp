@@ -143,7 +143,11 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
   PF_TRY(launch_copy_state(x->fec, z.stc, x->tfec, z.stc, z.stc, B, s));
   PF_TRY(launch_copy_state(x->fic, z.stc, x->tfic, z.stc, z.stc, B, s));
   PF_TRY(launch_fas_tau(x->f, x->c, dt, fef, fif, x->fec, x->fic, x->tau, B, s));
-  // C) serial coarse chain
+  // C) serial coarse chain.  On the fused small-batch path a step leaves the
+  // assembly of F_E at its last node to the next step's first node kernel
+  // (the same kernels' arithmetic in one launch fewer per step).
+  const bool fused_c = node_fused_ok(x->c, mem);
+  bool pending = false;
   for (int n = 0; n < x->n_ts; ++n) {
     const size_t o = 2 * (size_t)n * mem * z.stc;
     double* th = x->thc + o;
@@ -153,8 +157,11 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     if (n >= 1) {
       const size_t last = 2 * ((size_t)(n - 1) * mem * z.stc + (size_t)Mc * z.n3kc);
       src = StepSrc{x->thc + last, x->fec + last, x->fic + last, z.stc};
+      if (pending) src.fe_pending = x->fec + last;
     }
-    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s, src));
+    const bool defer = fused_c && n + 1 < x->n_ts;
+    PF_TRY(sweep_impl(x->c, dt, th, fe, fi, x->tau + o, mem, s, src, defer));
+    pending = defer;
   }
   // D) interpolate the coarse increments; new fine initial conditions
   PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->tthc, thf, B, s));

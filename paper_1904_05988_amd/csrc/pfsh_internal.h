@@ -170,15 +170,22 @@ struct StepSrc {
   const double* fe = nullptr;
   const double* fi = nullptr;
   long long stride = 0;   // complex values between batch entries
+  // non-null (fused small-batch path only): F_E at the source node is not yet
+  // assembled; it is the analysis of this level's current ring output (the
+  // source step's last node), written here (the same array as fe) first
+  double* fe_pending = nullptr;
 };
 
 // Compositions of the kernels above (api.cpp): the RHS of strided states; one
 // sweep (its node 0 optionally received from `src` first).
 hipError_t rhs_strided(const pfsh_level* lv, const double* state, long long sstride, double* fe,
                        long long fes, double* fi, long long fis, int batch, hipStream_t s);
+// defer_last (fused small-batch path only): leave F_E of the last node to the
+// next sweep on this level, which takes this sweep's last node as its source
+// with fe_pending set.
 hipError_t sweep_impl(const pfsh_level* lv, double dt, double* th, double* fe, double* fi,
                       const double* tau, int batch, hipStream_t s,
-                      const StepSrc& src = StepSrc());
+                      const StepSrc& src = StepSrc(), bool defer_last = false);
 
 // Sweep node `node` (1..M) fused with the F_E assembly of node `asm_node`
 // (-1: none), the old-iterate accumulation (node 1, optionally taking node 0
