@@ -216,7 +216,8 @@ pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, in
  *            block per wave, t4 = one wave of 64 x 64 per workgroup
  *            (FP64 / FP32: (4,0) (2,0) (8,0) (4,1) (8,1) (4,t4) (2,t4);
  *            BF16x3: (2,0) (4,0) (2,1) (4,1));
- *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4;
+ *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4 with
+ *            256 threads per workgroup, radix 16 with 512 threads;
  *   stage 3, sweep path for batches of 1-2 slices on FP64 / FP32 levels:
  *            0 = one fused kernel per node and order (Legendre analysis of the
  *            previous node's products, F_E assembly, node update, Legendre

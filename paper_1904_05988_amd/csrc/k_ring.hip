@@ -329,8 +329,8 @@ __device__ __forceinline__ void split_pair(const cpx<R>* sig, int N, int m, cpx<
   ys = {(R)0.5 * (z.y + w.y), (R)0.5 * (w.x - z.x)};
 }
 
-template <class Op, int N, int CAP>
-__global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restrict__ F4,
+template <class Op, int N, int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_ring_rhs(const typename Op::R* __restrict__ F4,
                                                  void* __restrict__ G,
                                                  const double* __restrict__ mu,
                                                  const double* __restrict__ wq,
@@ -341,7 +341,6 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   cpx<R>* twl = buf + 5 * SP;
-  constexpr int NT = 256;
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const cpx<R>* tw = Twiddles<R, N, CAP>::setup(twl, twg);
   // orders L .. N - L carry no coefficient; the loads below fill the others
@@ -369,7 +368,7 @@ __global__ __launch_bounds__(256) void k_ring_rhs(const typename Op::R* __restri
   };
   constexpr int SL = nstages(N, CAP) - 1;                 // last stage: NB = NS = N / RAD
   constexpr int RL = radix_of(N, SL, CAP), NBL = N / RL;
-  if constexpr (NBL % NT == 0 && NBL % 16 == 0) {
+  if constexpr (NBL % 16 == 0) {
     // The last inverse stage and the products in one pass: a thread owns
     // butterfly j of all four signals, whose outputs j + r NB are the points
     // it read, so nothing else touches them before the next barrier.
@@ -496,7 +495,7 @@ __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ gr
 }
 
 // ---------------------------------------------------------------- dispatch
-template <class Op, int N, int CAP>
+template <class Op, int N, int CAP, int NT = 256>
 static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const double* gin,
                               double* gout, hipStream_t s) {
   typedef typename Op::R R;
@@ -507,9 +506,9 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
     shm = (size_t)5 * padded_len(N) * sizeof(cpx<R>) +
           (size_t)Twiddles<R, N, CAP>::kLdsElems * sizeof(cpx<R>);
     if (shm > 65536)
-      (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP>,
+      (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP, NT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP>), dim3(lv->J, count), dim3(256), shm, s,
+    hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP, NT>), dim3(lv->J, count), dim3(NT), shm, s,
                        (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->Lp, lv->kb2g,
                        lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
@@ -530,9 +529,11 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
   return hipGetLastError();
 }
 
-// Ring-stage variants (index 0 = default): the largest FFT radix, 16, 8 or 4
-// (RHS kernel only; the scalar transforms use 16).
-int ring_variant_count() { return 3; }
+// Ring-stage variants (index 0 = default): the largest FFT radix, 16, 8 or 4,
+// with 256 threads per workgroup, and radix 16 with 512 threads (twice the
+// waves per CU where the LDS of a ring pair allows few workgroups, e.g. FP64 or
+// T511); RHS kernel only, the scalar transforms use radix 16 and 256 threads.
+int ring_variant_count() { return 4; }
 
 template <class Op, int N>
 static hipError_t ring_cap(int kind, const pfsh_level* lv, int count, const double* gin,
@@ -540,6 +541,7 @@ static hipError_t ring_cap(int kind, const pfsh_level* lv, int count, const doub
   const int v = kind == 0 ? lv->variant[TS_RING][tune_bucket(count)] : 0;
   if (v == 1) return ring_launch<Op, N, 8>(kind, lv, count, gin, gout, s);
   if (v == 2) return ring_launch<Op, N, 4>(kind, lv, count, gin, gout, s);
+  if (v == 3) return ring_launch<Op, N, 16, 512>(kind, lv, count, gin, gout, s);
   return ring_launch<Op, N, 16>(kind, lv, count, gin, gout, s);
 }
 
