@@ -113,42 +113,84 @@ struct OpBF3 {
 };
 
 // K loop of one wave's 2x2 blocks: A blocks at ta, ta+1 (+astep per k-block),
-// B blocks at tb, tb+1 (+bstep).  Operands are loaded PF k-blocks ahead into a
-// register ring, so the memory latency overlaps PF k-blocks of matrix work.
+// B blocks at tb, tb+1 (+bstep); R1 / C1: the second block row / column
+// exists.  Operands are loaded PF k-blocks ahead into a register ring, so the
+// memory latency overlaps PF k-blocks of matrix work.  The loop body has no
+// branches (prefetch addresses past the last k-block are clamped to it, and
+// those copies are never used; the last nk mod PF k-blocks run in a tail), so
+// every MFMA waits only for its own operands.
+// A wave-uniform value moved to scalar registers (address arithmetic on the
+// scalar unit; only the lane offset stays per lane).
+__device__ __forceinline__ long long wave_uniform(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v & 0xffffffffu));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+template <class Op, int PF, bool R1, bool C1>
+__device__ __forceinline__ void mma_loop_rc(const void* __restrict__ A, const void* __restrict__ B,
+                                            long long ta, long long astep, long long tb,
+                                            long long bstep, int nk, int lane,
+                                            typename Op::C& acc00, typename Op::C& acc01,
+                                            typename Op::C& acc10, typename Op::C& acc11) {
+  ta = wave_uniform(ta);
+  tb = wave_uniform(tb);
+  astep = wave_uniform(astep);
+  bstep = wave_uniform(bstep);
+  nk = __builtin_amdgcn_readfirstlane(nk);
+  if (nk <= 0) return;
+  typename Op::A a0[PF], a1[PF], b0[PF], b1[PF];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) {
+    const long long k = s < nk ? s : nk - 1;
+    a0[s] = Op::load(A, ta + k * astep, lane);
+    if (R1) a1[s] = Op::load(A, ta + k * astep + 1, lane);
+    b0[s] = Op::load(B, tb + k * bstep, lane);
+    if (C1) b1[s] = Op::load(B, tb + k * bstep + 1, lane);
+  }
+  int k0 = 0;
+  for (; k0 + PF <= nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      acc00 = Op::mma(a0[s], b0[s], acc00);
+      if (C1) acc01 = Op::mma(a0[s], b1[s], acc01);
+      if (R1) acc10 = Op::mma(a1[s], b0[s], acc10);
+      if (R1 && C1) acc11 = Op::mma(a1[s], b1[s], acc11);
+      const int kn = k0 + s + PF;
+      const long long k = kn < nk ? kn : nk - 1;
+      a0[s] = Op::load(A, ta + k * astep, lane);
+      if (R1) a1[s] = Op::load(A, ta + k * astep + 1, lane);
+      b0[s] = Op::load(B, tb + k * bstep, lane);
+      if (C1) b1[s] = Op::load(B, tb + k * bstep + 1, lane);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s) {
+    if (k0 + s < nk) {
+      acc00 = Op::mma(a0[s], b0[s], acc00);
+      if (C1) acc01 = Op::mma(a0[s], b1[s], acc01);
+      if (R1) acc10 = Op::mma(a1[s], b0[s], acc10);
+      if (R1 && C1) acc11 = Op::mma(a1[s], b1[s], acc11);
+    }
+  }
+}
+
+// The 2x2 K loop with the edge flags taken once per wave.  Every argument but
+// the accumulators and `lane` must be uniform over the wave.
 template <class Op, int PF>
 __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void* __restrict__ B,
                                          long long ta, long long astep, long long tb,
                                          long long bstep, int nk, bool r1, bool c1, int lane,
                                          typename Op::C& acc00, typename Op::C& acc01,
                                          typename Op::C& acc10, typename Op::C& acc11) {
-  typename Op::A a0[PF], a1[PF], b0[PF], b1[PF];
-#pragma unroll
-  for (int s = 0; s < PF; ++s) {
-    const bool ok = s < nk;
-    a0[s] = ok ? Op::load(A, ta + s * astep, lane) : Op::zero();
-    b0[s] = ok ? Op::load(B, tb + s * bstep, lane) : Op::zero();
-    a1[s] = (ok && r1) ? Op::load(A, ta + s * astep + 1, lane) : Op::zero();
-    b1[s] = (ok && c1) ? Op::load(B, tb + s * bstep + 1, lane) : Op::zero();
-  }
-  for (int k0 = 0; k0 < nk; k0 += PF) {
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      const int kb = k0 + s;
-      if (kb < nk) {
-        acc00 = Op::mma(a0[s], b0[s], acc00);
-        if (c1) acc01 = Op::mma(a0[s], b1[s], acc01);
-        if (r1) acc10 = Op::mma(a1[s], b0[s], acc10);
-        if (r1 && c1) acc11 = Op::mma(a1[s], b1[s], acc11);
-        const int kn = kb + PF;
-        if (kn < nk) {
-          a0[s] = Op::load(A, ta + kn * astep, lane);
-          b0[s] = Op::load(B, tb + kn * bstep, lane);
-          if (r1) a1[s] = Op::load(A, ta + kn * astep + 1, lane);
-          if (c1) b1[s] = Op::load(B, tb + kn * bstep + 1, lane);
-        }
-      }
-    }
-  }
+  if (r1 && c1)
+    mma_loop_rc<Op, PF, true, true>(A, B, ta, astep, tb, bstep, nk, lane, acc00, acc01, acc10, acc11);
+  else if (r1)
+    mma_loop_rc<Op, PF, true, false>(A, B, ta, astep, tb, bstep, nk, lane, acc00, acc01, acc10, acc11);
+  else if (c1)
+    mma_loop_rc<Op, PF, false, true>(A, B, ta, astep, tb, bstep, nk, lane, acc00, acc01, acc10, acc11);
+  else
+    mma_loop_rc<Op, PF, false, false>(A, B, ta, astep, tb, bstep, nk, lane, acc00, acc01, acc10, acc11);
 }
 
 // K loop of one wave's RT x CT blocks (rows ta + r, columns tb + c; r < nr,
