@@ -197,11 +197,64 @@ __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void*
 // c < nc valid): RT + CT operand loads feed RT CT MFMAs per k-block, so larger
 // tiles re-read the operands fewer times.  Every block accumulates its k-blocks
 // in the same order as mma_loop, so the results are the same bits.
+// Full RT x CT tile: the branch-free form of mma_loop_rc (clamped prefetch,
+// scalar addresses, tail after the loop).
+template <class Op, int PF, int RT, int CT>
+__device__ __forceinline__ void mma_tile_full(const void* __restrict__ A, const void* __restrict__ B,
+                                              long long ta, long long astep, long long tb,
+                                              long long bstep, int nk, int lane,
+                                              typename Op::C (&acc)[RT][CT]) {
+  ta = wave_uniform(ta);
+  tb = wave_uniform(tb);
+  astep = wave_uniform(astep);
+  bstep = wave_uniform(bstep);
+  nk = __builtin_amdgcn_readfirstlane(nk);
+  if (nk <= 0) return;
+  typename Op::A a[PF][RT], b[PF][CT];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) {
+    const long long k = s < nk ? s : nk - 1;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[s][r] = Op::load(A, ta + k * astep + r, lane);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[s][c] = Op::load(B, tb + k * bstep + c, lane);
+  }
+  int k0 = 0;
+  for (; k0 + PF <= nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[r][c] = Op::mma(a[s][r], b[s][c], acc[r][c]);
+      const int kn = k0 + s + PF;
+      const long long k = kn < nk ? kn : nk - 1;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) a[s][r] = Op::load(A, ta + k * astep + r, lane);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[s][c] = Op::load(B, tb + k * bstep + c, lane);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s) {
+    if (k0 + s < nk) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[r][c] = Op::mma(a[s][r], b[s][c], acc[r][c]);
+    }
+  }
+}
+
 template <class Op, int PF, int RT, int CT>
 __device__ __forceinline__ void mma_tile(const void* __restrict__ A, const void* __restrict__ B,
                                          long long ta, long long astep, long long tb,
                                          long long bstep, int nk, int nr, int nc, int lane,
                                          typename Op::C (&acc)[RT][CT]) {
+  if (__builtin_amdgcn_readfirstlane(nr) == RT && __builtin_amdgcn_readfirstlane(nc) == CT) {
+    mma_tile_full<Op, PF, RT, CT>(A, B, ta, astep, tb, bstep, nk, lane, acc);
+    return;
+  }
   typename Op::A a[PF][RT], b[PF][CT];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {
