@@ -210,41 +210,69 @@ __device__ __forceinline__ Bf16Pair load_g_bf3(const float* __restrict__ g, long
 }
 
 // K loop of one wave's 2x2 BF16x3 blocks with the B operand converted on load;
-// g0 = this lane's first float (k-block 0, column block cb0).
+// g0 = this lane's first float (k-block 0, column block cb0).  Branch-free like
+// mma_loop_rc: edge flags as template arguments, clamped prefetch, a tail.
+template <int PF, bool R1, bool C1>
+__device__ __forceinline__ void mma_loop_bf3g_rc(const void* __restrict__ A,
+                                                 const float* __restrict__ G, long long ta,
+                                                 long long astep, long long g0, long long gstep,
+                                                 long long next, long long gcol, int nk, int lane,
+                                                 f4_t& acc00, f4_t& acc01, f4_t& acc10,
+                                                 f4_t& acc11) {
+  ta = wave_uniform(ta);
+  astep = wave_uniform(astep);
+  nk = __builtin_amdgcn_readfirstlane(nk);
+  if (nk <= 0) return;
+  Bf16Pair a0[PF], a1[PF], b0[PF], b1[PF];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) {
+    const long long k = s < nk ? s : nk - 1;
+    a0[s] = OpBF3::load(A, ta + k * astep, lane);
+    if (R1) a1[s] = OpBF3::load(A, ta + k * astep + 1, lane);
+    b0[s] = load_g_bf3(G + g0 + k * gstep, next);
+    if (C1) b1[s] = load_g_bf3(G + g0 + k * gstep + gcol, next);
+  }
+  int k0 = 0;
+  for (; k0 + PF <= nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      acc00 = OpBF3::mma(a0[s], b0[s], acc00);
+      if (C1) acc01 = OpBF3::mma(a0[s], b1[s], acc01);
+      if (R1) acc10 = OpBF3::mma(a1[s], b0[s], acc10);
+      if (R1 && C1) acc11 = OpBF3::mma(a1[s], b1[s], acc11);
+      const int kn = k0 + s + PF;
+      const long long k = kn < nk ? kn : nk - 1;
+      a0[s] = OpBF3::load(A, ta + k * astep, lane);
+      if (R1) a1[s] = OpBF3::load(A, ta + k * astep + 1, lane);
+      b0[s] = load_g_bf3(G + g0 + k * gstep, next);
+      if (C1) b1[s] = load_g_bf3(G + g0 + k * gstep + gcol, next);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s) {
+    if (k0 + s < nk) {
+      acc00 = OpBF3::mma(a0[s], b0[s], acc00);
+      if (C1) acc01 = OpBF3::mma(a0[s], b1[s], acc01);
+      if (R1) acc10 = OpBF3::mma(a1[s], b0[s], acc10);
+      if (R1 && C1) acc11 = OpBF3::mma(a1[s], b1[s], acc11);
+    }
+  }
+}
+
 template <int PF>
 __device__ __forceinline__ void mma_loop_bf3g(const void* __restrict__ A, const float* __restrict__ G,
                                               long long ta, long long astep, long long g0,
                                               long long gstep, long long next, long long gcol,
                                               int nk, bool r1, bool c1, int lane,
                                               f4_t& acc00, f4_t& acc01, f4_t& acc10, f4_t& acc11) {
-  Bf16Pair a0[PF], a1[PF], b0[PF], b1[PF];
-#pragma unroll
-  for (int s = 0; s < PF; ++s) {
-    const bool ok = s < nk;
-    a0[s] = ok ? OpBF3::load(A, ta + s * astep, lane) : OpBF3::zero();
-    a1[s] = (ok && r1) ? OpBF3::load(A, ta + s * astep + 1, lane) : OpBF3::zero();
-    b0[s] = ok ? load_g_bf3(G + g0 + s * gstep, next) : OpBF3::zero();
-    b1[s] = (ok && c1) ? load_g_bf3(G + g0 + s * gstep + gcol, next) : OpBF3::zero();
-  }
-  for (int k0 = 0; k0 < nk; k0 += PF) {
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      const int kb = k0 + s;
-      if (kb < nk) {
-        acc00 = OpBF3::mma(a0[s], b0[s], acc00);
-        if (c1) acc01 = OpBF3::mma(a0[s], b1[s], acc01);
-        if (r1) acc10 = OpBF3::mma(a1[s], b0[s], acc10);
-        if (r1 && c1) acc11 = OpBF3::mma(a1[s], b1[s], acc11);
-        const int kn = kb + PF;
-        if (kn < nk) {
-          a0[s] = OpBF3::load(A, ta + kn * astep, lane);
-          b0[s] = load_g_bf3(G + g0 + kn * gstep, next);
-          if (r1) a1[s] = OpBF3::load(A, ta + kn * astep + 1, lane);
-          if (c1) b1[s] = load_g_bf3(G + g0 + kn * gstep + gcol, next);
-        }
-      }
-    }
-  }
+  if (r1 && c1)
+    mma_loop_bf3g_rc<PF, true, true>(A, G, ta, astep, g0, gstep, next, gcol, nk, lane, acc00, acc01, acc10, acc11);
+  else if (r1)
+    mma_loop_bf3g_rc<PF, true, false>(A, G, ta, astep, g0, gstep, next, gcol, nk, lane, acc00, acc01, acc10, acc11);
+  else if (c1)
+    mma_loop_bf3g_rc<PF, false, true>(A, G, ta, astep, g0, gstep, next, gcol, nk, lane, acc00, acc01, acc10, acc11);
+  else
+    mma_loop_bf3g_rc<PF, false, false>(A, G, ta, astep, g0, gstep, next, gcol, nk, lane, acc00, acc01, acc10, acc11);
 }
 
 template <class Op, int PF, int SHAPE>
