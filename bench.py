@@ -159,11 +159,15 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
         fine_b = [B] if args.schedule == "iterations" else sorted({B, 8, 4, 2, 1}, reverse=True)
         coarse_b = sorted({MEMBERS, 2 * MEMBERS, 4 * MEMBERS, 8 * MEMBERS, B} & set(range(1, B + 1)))
         coarse_b.append(B * nnc)
+        # The fine levels are tuned with cold caches: in a block the other
+        # kernels of a sweep evict the tables between two launches of a stage.
+        # The coarse chain runs its stages back to back (hot caches).
         for name, lv, batches in (("fine", gfm, fine_b + [B * nnf]), ("fine_fp64", gf64, fine_b),
                                   ("coarse", gc, coarse_b)):
             if name == "fine_fp64" and gf64 is gfm:
                 continue
-            tuned[name] = {b: {k: v[0] for k, v in lv.autotune(b, reps=10).items()} for b in batches}
+            tuned[name] = {b: {k: v[0] for k, v in lv.autotune(b, reps=10, cold=name != "coarse").items()}
+                           for b in batches}
         torch.cuda.synchronize()
 
     def block():

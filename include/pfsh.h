@@ -244,6 +244,14 @@ pfsh_status pfsh_level_set_variant(pfsh_level* level, int stage, int batch, int 
 pfsh_status pfsh_level_get_variant(const pfsh_level* level, int stage, int batch, int* variant);
 pfsh_status pfsh_level_autotune(pfsh_level* level, int batch, int reps, void* stream,
                                 float* us_out);
+/* The same with flags: PFSH_TUNE_COLD times each launch alone after rewriting a
+ * 512 MiB buffer (allocated and freed inside the call; PFSH_ENOMEM if it cannot
+ * be), so that tables and operands come from HBM as they do between the other
+ * kernels of a sweep; without it the launches run back to back with hot caches.
+ * Other bits: PFSH_EINVAL. */
+#define PFSH_TUNE_COLD 1
+pfsh_status pfsh_level_autotune_ex(pfsh_level* level, int batch, int reps, int flags, void* stream,
+                                   float* us_out);
 
 /* ---------------------------------------------------------------------------
  * Two-level PFASST on one device (Sec. 5.2).  The n_ts time steps of a block

@@ -60,6 +60,7 @@ _SIGS = {
     "pfsh_level_set_variant": ([_P, _I, _I, _I], _I),
     "pfsh_level_get_variant": ([_P, _I, _I, ctypes.POINTER(_I)], _I),
     "pfsh_level_autotune": ([_P, _I, _I, _P, _P], _I),
+    "pfsh_level_autotune_ex": ([_P, _I, _I, _I, _P, _P], _I),
     "pfsh_pfasst_create": ([_P, _P, _I, _I, ctypes.POINTER(_P)], _I),
     "pfsh_pfasst_destroy": ([_P], None),
     "pfsh_pfasst_predict": ([_P, _D, _P, _P, _P, _P, _P], _I),
@@ -200,13 +201,17 @@ class Level:
                                             ctypes.byref(v)), "pfsh_level_get_variant")
         return v.value
 
-    def autotune(self, batch, reps=20):
+    TUNE_COLD = 1
+
+    def autotune(self, batch, reps=20, cold=False):
         """Time every transform-kernel variant at `batch` on the current stream
-        and keep the fastest; returns {stage: (chosen, [us per variant])}."""
+        and keep the fastest; cold: each launch timed after the caches are
+        rewritten.  Returns {stage: (chosen, [us per variant])}."""
         us = (ctypes.c_float * (3 * self.MAX_VARIANTS))()
         s = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
-        _check(lib().pfsh_level_autotune(self._h, int(batch), int(reps), s, us),
-               "pfsh_level_autotune")
+        _check(lib().pfsh_level_autotune_ex(self._h, int(batch), int(reps),
+                                            self.TUNE_COLD if cold else 0, s, us),
+               "pfsh_level_autotune_ex")
         out = {}
         for name in self.TUNED:
             st = self.STAGES[name]

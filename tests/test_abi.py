@@ -94,6 +94,7 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.pfsh_level_set_variant(None, 0, 1, 0) == -1
     assert L.pfsh_level_get_variant(None, 0, 1, ctypes.byref(v)) == -1
     assert L.pfsh_level_autotune(None, 1, 5, None, None) == -1
+    assert L.pfsh_level_autotune_ex(None, 1, 5, 1, None, None) == -1
     L.pfsh_level_destroy(None)
     L.pfsh_pfasst_destroy(None)
 

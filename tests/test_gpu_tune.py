@@ -50,8 +50,8 @@ def test_autotune_keeps_a_valid_choice_and_results():
     T, nlat, nlon, B = 63, 96, 192, 4
     gl, ol = level_pair(T, nlat, nlon, 3, max_batch=B)
     states = seeded(T, range(20, 20 + B))
-    for batch in (1, B):
-        out = gl.autotune(batch, reps=3)
+    for batch, cold in ((1, False), (B, False), (B, True)):
+        out = gl.autotune(batch, reps=3, cold=cold)
         for stage, (chosen, us) in out.items():
             assert len(us) == gl.variant_count(stage)
             assert 0 <= chosen < len(us)
