@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
     mma_loop<Op, PF>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
                      (long long)CBa, kb2, r1, c1, lane, acc00, acc01, acc10, acc11);
   }
-  const int base = ext_off(T, q.m);
+  const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
   auto put = [&](const typename Op::C& acc, int rb, int cb) {
     const int c = cb * 16 + (lane & 15);
     if (c >= ncols) return;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
     for (int v = 0; v < 4; ++v) {
       const int i = rb * 16 + Op::row(lane, v);
       if (i < q.np)
-        Y[((size_t)(c >> 1) * Kx + base + q.p + 2 * i) * 2 + (c & 1)] = (typename Op::R)acc[v];
+        Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (typename Op::R)acc[v];
     }
   };
   put(acc00, rb0, cb0);
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(64) void k_leg_anal_t4(const void* __restrict__ tab
   typename Op::C acc[4][4] = {};
   mma_tile<Op, PF, 4, 4>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
                          (long long)CBa, kb2, nr, nc, lane, acc);
-  const int base = ext_off(T, q.m);
+  const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(64) void k_leg_anal_t4(const void* __restrict__ tab
       for (int v = 0; v < 4; ++v) {
         const int i = (rb0 + r) * 16 + Op::row(lane, v);
         if (i < q.np)
-          Y[((size_t)(c >> 1) * Kx + base + q.p + 2 * i) * 2 + (c & 1)] = (typename Op::R)acc[r][cb][v];
+          Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (typename Op::R)acc[r][cb][v];
       }
     }
 }

@@ -183,7 +183,7 @@ __global__ void k_unpack_scalar(const R* __restrict__ Y, double* __restrict__ sp
     const int f = (int)(idx / K), k = (int)(idx - (long long)f * K);
     int m, n;
     slot_mn(T, k, m, n);
-    const R* y = Y + 2 * ((size_t)f * Kx + ext_off(T, m) + n - m);
+    const R* y = Y + 2 * ((size_t)f * Kx + ext_pos(T, m, n));
     st2(spec + 2 * idx, {(double)y[0], m == 0 ? 0.0 : (double)y[1]});
   }
 }
@@ -221,13 +221,15 @@ __device__ __forceinline__ void assemble_core(GetY get, int m, int n, double a, 
   }
 }
 
-// Products of one slice in global memory, Yb = [5 products][Kx] complex.
+// Products of one slice in global memory, Yb = [5 products][Kx] complex, each
+// order's degrees parity-split from eoff = ext_off(T, m) (ext_pos).
 template <typename R>
 __device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, int eoff, int m,
                                               int n, int T, double a, C2 out[3]) {
+  const int np0 = npar(T, m, 0);
   auto get = [&](int f, int nn) -> C2 {
     if (nn < m || nn > T + 1) return {0.0, 0.0};
-    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + nn - m);
+    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + ((nn - m) & 1 ? np0 : 0) + ((nn - m) >> 1));
     return {(double)p[0], (double)p[1]};
   };
   assemble_core(get, m, n, a, out);

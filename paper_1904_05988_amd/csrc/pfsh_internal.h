@@ -21,6 +21,13 @@ __host__ __device__ inline int ext_off(int T, int m) { return m * (T + 2) - m * 
 __host__ __device__ inline int npar(int T, int m, int p) {
   return (m + p <= T + 1) ? ((T + 1 - m - p) / 2 + 1) : 0;
 }
+// Position of degree n (m <= n <= T+1) of order m in the analysis output: per
+// order the degrees of parity 0 (n - m even) first, then those of parity 1, so
+// that the workgroup of one parity writes whole cache lines.
+__host__ __device__ inline int ext_pos(int T, int m, int n) {
+  const int d = n - m;
+  return ext_off(T, m) + ((d & 1) ? npar(T, m, 0) : 0) + (d >> 1);
+}
 
 // MFMA operand blocks.  FP64/FP32 use 16x16x4 MFMA: a block is 16 (row or
 // column) x 4 (k) elements and lane l holds element (l % 16, l / 16).  BF16x3
