@@ -335,13 +335,22 @@ __global__ __launch_bounds__(NT) void k_ring_rhs(const typename Op::R* __restric
                                                  const double* __restrict__ mu,
                                                  const double* __restrict__ wq,
                                                  const cpx<typename Op::R>* __restrict__ twg, int J,
-                                                 int L, int Lp, int kb2, int CBa, double two_omega) {
+                                                 int nstate, int L, int Lp, int kb2, int CBa,
+                                                 double two_omega) {
   typedef typename Op::R R;
   constexpr int SP = padded_len(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   cpx<R>* twl = buf + 5 * SP;
-  const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  // Block id -> (ring pair j, state b), XCD-aware: the hardware deals block ids
+  // to the 8 XCDs in turn, so XCD x takes the contiguous range [x per, (x+1) per)
+  // of (j, b) with b fastest.  The workgroups that write the same cache lines
+  // of the analysis operand (ring pairs j, j^1 and neighbouring states) then run
+  // on one XCD close in time, and its L2 merges their partial lines.
+  const int nwg = J * nstate, per = (nwg + 7) / 8;
+  const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (t >= nwg) return;                                 // whole workgroup, before any barrier
+  const int j = t / nstate, b = t - j * nstate, tid = threadIdx.x;
   const cpx<R>* tw = Twiddles<R, N, CAP>::setup(twl, twg);
   // orders L .. N - L carry no coefficient; the loads below fill the others
   for (int t = L + tid; t <= N - L; t += NT) {
@@ -508,9 +517,10 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP, NT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP, NT>), dim3(lv->J, count), dim3(NT), shm, s,
-                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, lv->L, lv->Lp, lv->kb2g,
-                       lv->CBa, 2.0 * lv->d.omega);
+    const int per = (lv->J * count + 7) / 8;
+    hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP, NT>), dim3(8 * per), dim3(NT), shm, s,
+                       (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, count, lv->L, lv->Lp,
+                       lv->kb2g, lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
     shm = (size_t)4 * padded_len(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
