@@ -743,38 +743,55 @@ __global__ void k_restrict(const double* __restrict__ in, double* __restrict__ o
 }
 
 // interpolation of an increment: inout_f[b][i][v][kf(kc)] += sum_j Pi_fc[i][j] (new - old)[b][j][v][kc]
+// One thread per (b, v, kc): the nc coarse increments are loaded once and
+// spread to all nf fine nodes (node loops unrolled to the 9-node maximum, so
+// the per-node values stay in registers).
 __global__ void k_interp_add(const double* __restrict__ nw, const double* __restrict__ old,
                              double* __restrict__ io, int Tc, int Tf, int nc, int nf, int batch,
                              TMat pm) {
   const int Kc = (Tc + 1) * (Tc + 2) / 2, Kf = (Tf + 1) * (Tf + 2) / 2;
-  const long long tot = (long long)batch * nf * 3 * Kc;
+  const long long tot = (long long)batch * 3 * Kc;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
        idx += (long long)gridDim.x * blockDim.x) {
     long long r = idx;
     const int kc = (int)(r % Kc); r /= Kc;
-    const int v = (int)(r % 3); r /= 3;
-    const int i = (int)(r % nf);
-    const int b = (int)(r / nf);
+    const int v = (int)(r % 3);
+    const int b = (int)(r / 3);
     int m, n;
     slot_mn(Tc, kc, m, n);
     const int kf = spec_off(Tf, m) + n - m;
-    double sx = 0, sy = 0;
-    for (int j = 0; j < nc; ++j) {
-      const double c = pm.P[i * nc + j];
-      if (c == 0.0) continue;
-      const size_t o = (((size_t)b * nc + j) * 3 + v) * Kc + kc;
-      C2 z = ld2(nw + 2 * o);
-      if (old) {
-        const C2 y = ld2(old + 2 * o);
-        z.x -= y.x;
-        z.y -= y.y;
+    C2 dz[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      if (j < nc) {
+        const size_t o = (((size_t)b * nc + j) * 3 + v) * Kc + kc;
+        dz[j] = ld2(nw + 2 * o);
+        if (old) {
+          const C2 y = ld2(old + 2 * o);
+          dz[j].x -= y.x;
+          dz[j].y -= y.y;
+        }
       }
-      sx += c * z.x;
-      sy += c * z.y;
     }
-    double* p = io + 2 * ((((size_t)b * nf + i) * 3 + v) * Kf + kf);
-    C2 t = ld2(p);
-    st2(p, {t.x + sx, t.y + sy});
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (i < nf) {
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+          if (j < nc) {
+            const double c = pm.P[i * nc + j];
+            if (c != 0.0) {
+              sx += c * dz[j].x;
+              sy += c * dz[j].y;
+            }
+          }
+        }
+        double* p = io + 2 * ((((size_t)b * nf + i) * 3 + v) * Kf + kf);
+        C2 t = ld2(p);
+        st2(p, {t.x + sx, t.y + sy});
+      }
+    }
   }
 }
 
@@ -797,34 +814,52 @@ __global__ void k_fas_tau(const double* __restrict__ fef, const double* __restri
     int m, n;
     slot_mn(Tc, kc, m, n);
     const int kf = spec_off(Tf, m) + n - m;
+    // node loops unrolled to the 9-node maximum: the per-node values stay in
+    // registers (runtime-indexed arrays would live in scratch memory)
     C2 Ff[9], Fc[9];
-    for (int l = 0; l < nf; ++l) {
-      const size_t o = (((size_t)b * nf + l) * 3 + v) * Kf + kf;
-      const C2 e = ld2(fef + 2 * o), f = ld2(fif + 2 * o);
-      Ff[l] = {e.x + f.x, e.y + f.y};
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      if (l < nf) {
+        const size_t o = (((size_t)b * nf + l) * 3 + v) * Kf + kf;
+        const C2 e = ld2(fef + 2 * o), f = ld2(fif + 2 * o);
+        Ff[l] = {e.x + f.x, e.y + f.y};
+      }
     }
-    for (int l = 0; l < nc; ++l) {
-      const size_t o = (((size_t)b * nc + l) * 3 + v) * Kc + kc;
-      const C2 e = ld2(fec + 2 * o), f = ld2(fic + 2 * o);
-      Fc[l] = {e.x + f.x, e.y + f.y};
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      if (l < nc) {
+        const size_t o = (((size_t)b * nc + l) * 3 + v) * Kc + kc;
+        const C2 e = ld2(fec + 2 * o), f = ld2(fic + 2 * o);
+        Fc[l] = {e.x + f.x, e.y + f.y};
+      }
     }
-    for (int i = 0; i < nc; ++i) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (i >= nc) continue;
       double fx = 0, fy = 0;
-      for (int j = 0; j < nf; ++j) {
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        if (j >= nf) continue;
         const double c = tm.Pcf[i * nf + j];
         if (c == 0.0) continue;
         double qx = 0, qy = 0;
-        for (int l = 0; l < nf; ++l) {
-          qx += tm.Qf[j * nf + l] * Ff[l].x;
-          qy += tm.Qf[j * nf + l] * Ff[l].y;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+          if (l < nf) {
+            qx += tm.Qf[j * nf + l] * Ff[l].x;
+            qy += tm.Qf[j * nf + l] * Ff[l].y;
+          }
         }
         fx += c * qx;
         fy += c * qy;
       }
       double cx = 0, cy = 0;
-      for (int l = 0; l < nc; ++l) {
-        cx += tm.Qc[i * nc + l] * Fc[l].x;
-        cy += tm.Qc[i * nc + l] * Fc[l].y;
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        if (l < nc) {
+          cx += tm.Qc[i * nc + l] * Fc[l].x;
+          cy += tm.Qc[i * nc + l] * Fc[l].y;
+        }
       }
       st2(tau + 2 * ((((size_t)b * nc + i) * 3 + v) * Kc + kc), {dt * fx - dt * cx, dt * fy - dt * cy});
     }
@@ -1084,7 +1119,7 @@ hipError_t launch_interp_add(const pfsh_level* c, const pfsh_level* f, const dou
                              const double* old_c, double* inout_f, int batch, hipStream_t s) {
   TMat pm;
   lagrange_matrix(c->nn, c->nodes, f->nn, f->nodes, pm.P);
-  const long long work = (long long)batch * f->nn * 3 * c->K;
+  const long long work = (long long)batch * 3 * c->K;
   hipLaunchKernelGGL(k_interp_add, dim3(nblocks(work, 256)), dim3(256), 0, s, new_c, old_c,
                      inout_f, c->T, f->T, c->nn, f->nn, batch, pm);
   return hipGetLastError();
