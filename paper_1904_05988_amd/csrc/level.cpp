@@ -140,10 +140,38 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
     return a.first > b.first;
   };
   std::stable_sort(ws.begin(), ws.end(), by_work);
-  std::stable_sort(wa.begin(), wa.end(), by_work);
   std::vector<WorkItem> its, ita;
   for (auto& x : ws) its.push_back(x.second);
-  for (auto& x : wa) ita.push_back(x.second);
+  // analysis: the degree tiles of one (m, p) all read its data operand, so they
+  // run back to back on one XCD (its L2 then serves the re-reads).  The kernel
+  // deals item i to XCD i mod 8, so (m, p) groups are assigned whole to the 8
+  // XCD sequences (heaviest group first, to the least loaded sequence) and the
+  // sequences interleaved; short sequences are padded with empty items (a tile
+  // past the last degree block, which the kernel skips).
+  {
+    std::vector<std::pair<long long, std::vector<WorkItem>>> groups;
+    for (auto& x : wa) {
+      if (groups.empty() || groups.back().second[0].mp != x.second.mp) groups.push_back({0, {}});
+      groups.back().first += x.first;
+      groups.back().second.push_back(x.second);
+    }
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    std::vector<WorkItem> seq[8];
+    long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (auto& g : groups) {
+      int x = 0;
+      for (int y = 1; y < 8; ++y)
+        if (load[y] < load[x]) x = y;
+      load[x] += g.first;
+      for (auto& w : g.second) seq[x].push_back(w);
+    }
+    size_t len = 0;
+    for (auto& q : seq) len = std::max(len, q.size());
+    const WorkItem empty{0, 1 << 20};
+    for (size_t k = 0; k < len; ++k)
+      for (int x = 0; x < 8; ++x) ita.push_back(k < seq[x].size() ? seq[x][k] : empty);
+  }
   lv->nitemsS = (int)its.size();
   lv->nitemsA = (int)ita.size();
 
