@@ -139,9 +139,8 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
   // B) restrict, coarse F, saved copies, tau
   PF_TRY(launch_restrict(x->f, x->c, thf, x->thc, B, s));
   PF_TRY(eval_all(x->c, x->thc, x->fec, x->fic, B, s));
-  PF_TRY(launch_copy_state(x->thc, z.stc, x->tthc, z.stc, z.stc, B, s));
-  PF_TRY(launch_copy_state(x->fec, z.stc, x->tfec, z.stc, z.stc, B, s));
-  PF_TRY(launch_copy_state(x->fic, z.stc, x->tfic, z.stc, z.stc, B, s));
+  PF_TRY(launch_copy_node3(x->thc, x->fec, x->fic, z.stc, x->tthc, x->tfec, x->tfic, z.stc, z.stc,
+                           B, s));
   PF_TRY(launch_fas_tau(x->f, x->c, dt, fef, fif, x->fec, x->fic, x->tau, B, s));
   // C) serial coarse chain.  On the fused small-batch path a step leaves the
   // assembly of F_E at its last node to the next step's first node kernel
@@ -215,9 +214,8 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
     // B) restrict, coarse F, saved copies, tau
     PF_TRY(launch_restrict(x->f, x->c, thf + of, x->thc + oc, nb, s));
     PF_TRY(eval_all(x->c, x->thc + oc, x->fec + oc, x->fic + oc, nb, s));
-    PF_TRY(launch_copy_state(x->thc + oc, z.stc, x->tthc + oc, z.stc, z.stc, nb, s));
-    PF_TRY(launch_copy_state(x->fec + oc, z.stc, x->tfec + oc, z.stc, z.stc, nb, s));
-    PF_TRY(launch_copy_state(x->fic + oc, z.stc, x->tfic + oc, z.stc, z.stc, nb, s));
+    PF_TRY(launch_copy_node3(x->thc + oc, x->fec + oc, x->fic + oc, z.stc, x->tthc + oc,
+                             x->tfec + oc, x->tfic + oc, z.stc, z.stc, nb, s));
     PF_TRY(launch_fas_tau(x->f, x->c, dt, fef + of, fif + of, x->fec + oc, x->fic + oc,
                           x->tau + oc, nb, s));
     // C) coarse initial conditions (and the F there) from the left neighbours
