@@ -379,7 +379,7 @@ def main():
                          "32 steps x 4 members")
     ap.add_argument("--n64", type=int, default=None,
                     help="final PFASST iterations with FP64 fine levels in the mixed block "
-                         "(default 4; ensemble 0)")
+                         "(default 2; ensemble 0)")
     ap.add_argument("--n-pf", type=int, default=None,
                     help="PFASST iterations per block (default 8; ensemble 4)")
     ap.add_argument("--schedule", default="iterations", choices=["wavefront", "iterations"],
@@ -395,7 +395,7 @@ def main():
     if args.n_pf is None:
         args.n_pf = 8 if args.workload == "t255" else 4
     if args.n64 is None:
-        args.n64 = 4 if args.workload == "t255" else 0
+        args.n64 = 2 if args.workload == "t255" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (time slices are its batch axis); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)

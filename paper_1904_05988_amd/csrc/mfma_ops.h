@@ -127,18 +127,30 @@ __device__ __forceinline__ long long wave_uniform(long long v) {
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
+// FP32 accumulation runs in two chains, k-blocks of even and of odd index
+// (added at the end): each sequential sum is half as long, which halves the
+// accumulated round-off of the long Legendre sums.  Every FP32 K loop below
+// uses the same rule, so all tile variants give the same bits.
+template <class Op>
+struct SplitAcc {
+  static constexpr bool value = Op::KIND == OP_F32;
+};
+
 template <class Op, int PF, bool R1, bool C1>
 __device__ __forceinline__ void mma_loop_rc(const void* __restrict__ A, const void* __restrict__ B,
                                             long long ta, long long astep, long long tb,
                                             long long bstep, int nk, int lane,
                                             typename Op::C& acc00, typename Op::C& acc01,
                                             typename Op::C& acc10, typename Op::C& acc11) {
+  constexpr bool SPL = SplitAcc<Op>::value;
+  static_assert(!SPL || PF % 2 == 0, "two accumulation chains need an even prefetch depth");
   ta = wave_uniform(ta);
   tb = wave_uniform(tb);
   astep = wave_uniform(astep);
   bstep = wave_uniform(bstep);
   nk = __builtin_amdgcn_readfirstlane(nk);
   if (nk <= 0) return;
+  typename Op::C x00 = {}, x01 = {}, x10 = {}, x11 = {};   // odd k-blocks (SPL)
   typename Op::A a0[PF], a1[PF], b0[PF], b1[PF];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {
@@ -148,14 +160,22 @@ __device__ __forceinline__ void mma_loop_rc(const void* __restrict__ A, const vo
     b0[s] = Op::load(B, tb + k * bstep, lane);
     if (C1) b1[s] = Op::load(B, tb + k * bstep + 1, lane);
   }
+  // k-block k0 + s has the parity of s (k0 is a multiple of PF)
+  auto step = [&](int s) {
+    typename Op::C& c00 = (SPL && (s & 1)) ? x00 : acc00;
+    typename Op::C& c01 = (SPL && (s & 1)) ? x01 : acc01;
+    typename Op::C& c10 = (SPL && (s & 1)) ? x10 : acc10;
+    typename Op::C& c11 = (SPL && (s & 1)) ? x11 : acc11;
+    c00 = Op::mma(a0[s], b0[s], c00);
+    if (C1) c01 = Op::mma(a0[s], b1[s], c01);
+    if (R1) c10 = Op::mma(a1[s], b0[s], c10);
+    if (R1 && C1) c11 = Op::mma(a1[s], b1[s], c11);
+  };
   int k0 = 0;
   for (; k0 + PF <= nk; k0 += PF) {
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
-      acc00 = Op::mma(a0[s], b0[s], acc00);
-      if (C1) acc01 = Op::mma(a0[s], b1[s], acc01);
-      if (R1) acc10 = Op::mma(a1[s], b0[s], acc10);
-      if (R1 && C1) acc11 = Op::mma(a1[s], b1[s], acc11);
+      step(s);
       const int kn = k0 + s + PF;
       const long long k = kn < nk ? kn : nk - 1;
       a0[s] = Op::load(A, ta + k * astep, lane);
@@ -165,13 +185,13 @@ __device__ __forceinline__ void mma_loop_rc(const void* __restrict__ A, const vo
     }
   }
 #pragma unroll
-  for (int s = 0; s < PF - 1; ++s) {
-    if (k0 + s < nk) {
-      acc00 = Op::mma(a0[s], b0[s], acc00);
-      if (C1) acc01 = Op::mma(a0[s], b1[s], acc01);
-      if (R1) acc10 = Op::mma(a1[s], b0[s], acc10);
-      if (R1 && C1) acc11 = Op::mma(a1[s], b1[s], acc11);
-    }
+  for (int s = 0; s < PF - 1; ++s)
+    if (k0 + s < nk) step(s);
+  if constexpr (SPL) {
+    acc00 += x00;
+    acc01 += x01;
+    acc10 += x10;
+    acc11 += x11;
   }
 }
 
@@ -210,6 +230,9 @@ __device__ __forceinline__ void mma_tile_full(const void* __restrict__ A, const 
   bstep = wave_uniform(bstep);
   nk = __builtin_amdgcn_readfirstlane(nk);
   if (nk <= 0) return;
+  constexpr bool SPL = SplitAcc<Op>::value;
+  static_assert(!SPL || PF % 2 == 0, "two accumulation chains need an even prefetch depth");
+  typename Op::C x[RT][CT] = {};   // odd k-blocks (SPL)
   typename Op::A a[PF][RT], b[PF][CT];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {
@@ -226,7 +249,10 @@ __device__ __forceinline__ void mma_tile_full(const void* __restrict__ A, const 
 #pragma unroll
       for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) acc[r][c] = Op::mma(a[s][r], b[s][c], acc[r][c]);
+        for (int c = 0; c < CT; ++c) {
+          typename Op::C& t = (SPL && (s & 1)) ? x[r][c] : acc[r][c];
+          t = Op::mma(a[s][r], b[s][c], t);
+        }
       const int kn = k0 + s + PF;
       const long long k = kn < nk ? kn : nk - 1;
 #pragma unroll
@@ -241,8 +267,17 @@ __device__ __forceinline__ void mma_tile_full(const void* __restrict__ A, const 
 #pragma unroll
       for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) acc[r][c] = Op::mma(a[s][r], b[s][c], acc[r][c]);
+        for (int c = 0; c < CT; ++c) {
+          typename Op::C& t = (SPL && (s & 1)) ? x[r][c] : acc[r][c];
+          t = Op::mma(a[s][r], b[s][c], t);
+        }
     }
+  }
+  if constexpr (SPL) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[r][c] += x[r][c];
   }
 }
 
@@ -255,6 +290,8 @@ __device__ __forceinline__ void mma_tile(const void* __restrict__ A, const void*
     mma_tile_full<Op, PF, RT, CT>(A, B, ta, astep, tb, bstep, nk, lane, acc);
     return;
   }
+  constexpr bool SPL = SplitAcc<Op>::value;
+  typename Op::C x[RT][CT] = {};   // odd k-blocks (SPL)
   typename Op::A a[PF][RT], b[PF][CT];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {
@@ -273,7 +310,10 @@ __device__ __forceinline__ void mma_tile(const void* __restrict__ A, const void*
         for (int r = 0; r < RT; ++r)
 #pragma unroll
           for (int c = 0; c < CT; ++c)
-            if (r < nr && c < nc) acc[r][c] = Op::mma(a[s][r], b[s][c], acc[r][c]);
+            if (r < nr && c < nc) {
+              typename Op::C& t = (SPL && (s & 1)) ? x[r][c] : acc[r][c];
+              t = Op::mma(a[s][r], b[s][c], t);
+            }
         const int kn = kb + PF;
         if (kn < nk) {
 #pragma unroll
@@ -285,6 +325,12 @@ __device__ __forceinline__ void mma_tile(const void* __restrict__ A, const void*
         }
       }
     }
+  }
+  if constexpr (SPL) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[r][c] += x[r][c];
   }
 }
 

@@ -92,14 +92,15 @@ def test_mixed_precision_sweep_error(t255_states, prec):
     assert np.all(after < worst), (prec, worst, after)
 
 
-def test_pfasst_mixed_block_with_fp64_finish_within_1e6():
+@pytest.mark.parametrize("n64", [2, 4])
+def test_pfasst_mixed_block_with_fp64_finish_within_1e6(n64):
     """PFASST(16, 5, 3, 8) at T255/T127 from seed 3: FP32 transforms, with the
-    last four iterations on FP64 fine levels, end within 1e-6 of the FP64
-    block (per variable).  The modes the coarse level also carries (n <= 127)
-    are pulled back to the FP64 iterate within a few FP64 iterations; the
-    rounding left above the coarse truncation is only carried along by the
-    fine sweeps and the initial-condition chain, which is where the rest of
-    the difference sits."""
+    last n64 iterations on FP64 fine levels (2 is the benchmark's recipe), end
+    within 1e-6 of the FP64 block (per variable), closer than all-FP32.  The
+    modes the coarse level also carries (n <= 127) are pulled back to the FP64
+    iterate by the FP64 iterations; the rounding left above the coarse
+    truncation is only carried along by the fine sweeps and the
+    initial-condition chain, which is where the rest of the difference sits."""
     fine, coarse = (255, 384, 768, 5), (127, 192, 384, 3)
     th0 = to_dev(inputs.seeded_state(255, 3)[None])
 
@@ -118,7 +119,7 @@ def test_pfasst_mixed_block_with_fp64_finish_within_1e6():
         return to_host(th)[:, -1]
 
     ref = block("fp64", 0)
-    got = block("fp32", 4)
+    got = block("fp32", n64)
     pure = block("fp32", 0)
     n = np.concatenate([np.arange(m, 256) for m in range(256)])
     err, err_low, err_pure = np.zeros(3), np.zeros(3), np.zeros(3)
@@ -129,8 +130,12 @@ def test_pfasst_mixed_block_with_fp64_finish_within_1e6():
         diff = got[s].copy()
         diff[:, n > 127] = ref[s][:, n > 127]
         err_low = np.maximum(err_low, rel_err(diff, ref[s]))
+    print("n64", n64, "err", err, "low modes", err_low, "all FP32", err_pure)
     assert np.all(err <= 1e-6), err
-    assert np.all(err_low <= 1e-7), err_low
+    # low modes: each FP64 iteration pulls them further back (measured, seed 3:
+    # divergence 1.6e-7 after two FP64 iterations, below 1e-7 after four)
+    assert np.all(err_low <= (3e-7 if n64 == 2 else 1e-7)), err_low
+    assert np.all(err_low <= err), (err_low, err)
     assert err[2] < err_pure[2], (err, err_pure)
 
 
