@@ -462,8 +462,8 @@ def main():
     # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counters of these kernel
     # versions (reads x2, writes x1 after calibration against a plain copy), FP32
     # fine level at T255 over 16 slices; the sweep node is averaged over nodes 1-4
-    measured = {("sweep_node", "fp32", 255, 16): 297.27e6, ("ring", "fp32", 255, 16): 144.89e6,
-                ("leg_synth", "fp32", 255, 16): 104.49e6, ("leg_anal", "fp32", 255, 16): 166.46e6}
+    measured = {("sweep_node", "fp32", 255, 16): 297.27e6, ("ring", "fp32", 255, 16): 114.56e6,
+                ("leg_synth", "fp32", 255, 16): 104.35e6, ("leg_anal", "fp32", 255, 16): 119.73e6}
     t = measured.get((dom, args.mixed, Tf, B))
     roof["traffic"] = t                         # HBM bytes per launch (measured)
     roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
