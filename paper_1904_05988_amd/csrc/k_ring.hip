@@ -40,6 +40,11 @@ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
 // accesses of the Stockham stages spread over the banks.
 __host__ __device__ constexpr int padded(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
+// Stride between signals: one element more than the padded length, so that the
+// same index of consecutive signals (read together when lanes run over the
+// fields) falls in different banks; padded lengths are often whole multiples
+// of the 128-byte bank row.
+__host__ __device__ constexpr int sig_stride(int n) { return padded_len(n) + 1; }
 
 // radix of stage s for a length-N transform with radices up to CAP (16, 8 or
 // 4): the largest first, then 8, 4, 2, then a 3
@@ -176,7 +181,7 @@ __device__ __forceinline__ void stage_twiddles(cpx<R>* v, const cpx<R>* tw, int 
 }
 
 // One Stockham stage on NSIG padded signals of length N stored back to back
-// in buf (stride padded_len(N)); twiddles from this stage's LDS table
+// in buf (stride sig_stride(N)); twiddles from this stage's LDS table
 // (TWLDS) or from the base table tw[t] = e^{2 pi i t / N}.  Element i of a
 // signal sits at padded(i).  When the RAD inputs j + r NB of a butterfly (and
 // its outputs base + r NS) stay in step with the padding -- NB (NS) a multiple
@@ -189,7 +194,7 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int TOT = NB * NSIG;
   constexpr int PER = (TOT + NT - 1) / NT;
   constexpr int STEP = N / (NS * RAD);
-  constexpr int SP = padded_len(N);
+  constexpr int SP = sig_stride(N);
   constexpr bool kInConst = NB % 16 == 0;
   constexpr bool kOutConst = NS % 16 == 0 || (NS == 1 && 16 % RAD == 0);
   constexpr int IN_STRIDE = padded_len(NB);
@@ -338,7 +343,7 @@ __global__ __launch_bounds__(NT) void k_ring_rhs(const typename Op::R* __restric
                                                  int nstate, int L, int Lp, int kb2, int CBa,
                                                  double two_omega) {
   typedef typename Op::R R;
-  constexpr int SP = padded_len(N);
+  constexpr int SP = sig_stride(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   cpx<R>* twl = buf + 5 * SP;
@@ -436,7 +441,7 @@ __global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __rest
                                                    const cpx<typename Op::R>* __restrict__ twg,
                                                    int J, int L, int Lp, int nf) {
   typedef typename Op::R R;
-  constexpr int SP = padded_len(N);
+  constexpr int SP = sig_stride(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   cpx<R>* twl = buf + 4 * SP;
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(256) void k_ring_anal(const double* __restrict__ gr
                                                   const cpx<typename Op::R>* __restrict__ twg,
                                                   int J, int L, int nf, int kb2, int CBa) {
   typedef typename Op::R R;
-  constexpr int SP = padded_len(N);
+  constexpr int SP = sig_stride(N);
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   cpx<R>* twl = buf + 4 * SP;
@@ -512,7 +517,7 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
   size_t shm;
   const size_t twl = (size_t)Twiddles<R, N, 16>::kLdsElems * sizeof(cpx<R>);
   if (kind == 0) {
-    shm = (size_t)5 * padded_len(N) * sizeof(cpx<R>) +
+    shm = (size_t)5 * sig_stride(N) * sizeof(cpx<R>) +
           (size_t)Twiddles<R, N, CAP>::kLdsElems * sizeof(cpx<R>);
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP, NT>,
@@ -522,14 +527,14 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
                        (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, count, lv->L, lv->Lp,
                        lv->kb2g, lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
-    shm = (size_t)4 * padded_len(N) * sizeof(cpx<R>) + twl;
+    shm = (size_t)4 * sig_stride(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_synth<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((k_ring_synth<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
                        (const R*)lv->F4, gout, tw, lv->J, lv->L, lv->Lp, count);
   } else {
-    shm = (size_t)4 * padded_len(N) * sizeof(cpx<R>) + twl;
+    shm = (size_t)4 * sig_stride(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_anal<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
