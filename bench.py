@@ -448,28 +448,35 @@ def main():
             return "hbm", sweep_node_bytes(Tf, nnf, B, rsz)
         return None, None
 
-    # the dominant kernel among those with a work model
-    dom = max((k for k in prof if kernel_work(k)[0]), key=lambda k: prof[k][1])
-    n, tot = prof[dom]
-    avg_s = tot / max(n, 1) * 1e-3
-    bound, work = kernel_work(dom)
-    if bound == "mfma":
-        roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAKS[args.mixed],
-                "unit": "TFLOP/s"}
+    # the dominant kernel among those with a work model and launches over all B
+    # slices (the wavefront schedule sweeps smaller groups of slices: then none)
+    cands = [k for k in prof if kernel_work(k)[0] and prof[k][0] > 0 and prof[k][1] > 0]
+    if not cands:
+        dom = None
+        roof = {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "note": f"no launch over all {B} slices in this schedule"}
     else:
-        roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+        dom = max(cands, key=lambda k: prof[k][1])
+        n, tot = prof[dom]
+        avg_s = tot / n * 1e-3
+        bound, work = kernel_work(dom)
+        if bound == "mfma":
+            roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAKS[args.mixed],
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
     # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counters of these kernel
     # versions (reads x2, writes x1 after calibration against a plain copy), FP32
     # fine level at T255 over 16 slices; the sweep node is averaged over nodes 1-4
     measured = {("sweep_node", "fp32", 255, 16): 297.27e6, ("ring", "fp32", 255, 16): 114.56e6,
                 ("leg_synth", "fp32", 255, 16): 104.35e6, ("leg_anal", "fp32", 255, 16): 119.73e6}
-    t = measured.get((dom, args.mixed, Tf, B))
-    roof["traffic"] = t                         # HBM bytes per launch (measured)
-    roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
-    roof["kernel"] = dom
-    roof["launches"] = n
-    roof["avg_us"] = avg_s * 1e6
+    if dom is not None:
+        roof["traffic"] = measured.get((dom, args.mixed, Tf, B))   # HBM bytes per launch (measured)
+        roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
+        roof["kernel"] = dom
+        roof["launches"] = n
+        roof["avg_us"] = avg_s * 1e6
 
     # every transform stage of the fine level against its own bound
     stages = {}
