@@ -8,13 +8,15 @@
 // (then 8/4/2 and a final radix 3): at every stage each thread reads its
 // butterflies' inputs into registers, the workgroup synchronizes, and the
 // outputs are written back in place; LDS signals are padded against bank
-// conflicts.
+// conflicts.  The last stage of the inverse transforms is fused with the grid
+// products (each thread owns its butterflies' points in all four fields).
 //
 // k_ring_rhs: Fourier coefficients of Phi', zeta, U = u cos(phi), V = v cos(phi)
 //   (parity form E/O per m) -> grid -> eta = zeta + 2 Omega mu, A = eta U,
 //   B = eta V, C = Phi' U, D = Phi' V, E = (U^2 + V^2)/2 -> Fourier coefficients
 //   weighted by w_j / ((1 - mu_j^2) nlon), in parity form (north +- south),
-//   written as the analysis data operand.
+//   written as the analysis data operand; workgroups are ordered XCD-aware.
+//   256 or 512 threads per workgroup (a tuner variant).
 // k_ring_synth / k_ring_anal: the same longitude step for scalar fields.
 #include "mfma_ops.h"
 
@@ -353,9 +355,9 @@ __global__ __launch_bounds__(NT) void k_ring_rhs(const typename Op::R* __restric
   // of the analysis operand (ring pairs j, j^1 and neighbouring states) then run
   // on one XCD close in time, and its L2 merges their partial lines.
   const int nwg = J * nstate, per = (nwg + 7) / 8;
-  const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (t >= nwg) return;                                 // whole workgroup, before any barrier
-  const int j = t / nstate, b = t - j * nstate, tid = threadIdx.x;
+  const int slot = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (slot >= nwg) return;                              // whole workgroup, before any barrier
+  const int j = slot / nstate, b = slot - j * nstate, tid = threadIdx.x;
   const cpx<R>* tw = Twiddles<R, N, CAP>::setup(twl, twg);
   // orders L .. N - L carry no coefficient; the loads below fill the others
   for (int t = L + tid; t <= N - L; t += NT) {
