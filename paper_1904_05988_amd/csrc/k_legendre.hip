@@ -12,10 +12,14 @@
 // Columns c = 2 (field + nf * batch) + {re, im}.  Degrees run to T+1 so that the
 // (1-mu^2) dP/dmu terms of the vector transforms fold into P contractions.
 //
-// One workgroup = 4 waves = one (m, p) and a 64-row x 64-column tile; every
-// wave owns 2x2 MFMA blocks of 16x16.  Operands are pre-packed in MFMA lane
-// order (tables at level creation, data by the producing kernels), so each
-// lane loads its fragment with one contiguous load.
+// Default tiles: analysis, one workgroup of 4 waves per (m, p) and 64 degrees x
+// 64 columns; synthesis, one wave per order for MC consecutive orders of one
+// parity, 32 rings x 32 columns each; every wave owns 2x2 MFMA blocks of 16x16.
+// Tuner variants change the prefetch depth and the tile (64 x 64 per wave,
+// one degree block per wave), never the order of a sum.  Operands are
+// pre-packed in MFMA lane order (tables at level creation, data by the
+// producing kernels), so each lane loads its fragment with one contiguous load;
+// the K loops (mfma_ops.h) run without branches, FP32 in two accumulation chains.
 #include "mfma_ops.h"
 
 namespace pfsh {
