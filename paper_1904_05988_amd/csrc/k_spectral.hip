@@ -746,9 +746,17 @@ __global__ void k_restrict(const double* __restrict__ in, double* __restrict__ o
 // One thread per (b, v, kc): the nc coarse increments are loaded once and
 // spread to all nf fine nodes (node loops unrolled to the 9-node maximum, so
 // the per-node values stay in registers).
-__global__ void k_interp_add(const double* __restrict__ nw, const double* __restrict__ old,
-                             double* __restrict__ io, int Tc, int Tf, int nc, int nf, int batch,
-                             TMat pm) {
+// Up to three (new, old, in-out) array triples, one per blockIdx.y (state, F_E,
+// F_I of PFASST step D in one launch).
+struct InterpArrays {
+  const double* nw[3];
+  const double* old[3];
+  double* io[3];
+};
+__global__ void k_interp_add(InterpArrays arr, int Tc, int Tf, int nc, int nf, int batch, TMat pm) {
+  const double* __restrict__ nw = arr.nw[blockIdx.y];
+  const double* __restrict__ old = arr.old[blockIdx.y];
+  double* __restrict__ io = arr.io[blockIdx.y];
   const int Kc = (Tc + 1) * (Tc + 2) / 2, Kf = (Tf + 1) * (Tf + 2) / 2;
   const long long tot = (long long)batch * 3 * Kc;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
@@ -1115,14 +1123,27 @@ hipError_t launch_restrict(const pfsh_level* f, const pfsh_level* c, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_interp_add(const pfsh_level* c, const pfsh_level* f, const double* new_c,
-                             const double* old_c, double* inout_f, int batch, hipStream_t s) {
+hipError_t launch_interp_add3(const pfsh_level* c, const pfsh_level* f, int count,
+                              const double* const* new_c, const double* const* old_c,
+                              double* const* inout_f, int batch, hipStream_t s) {
+  if (count < 1 || count > 3) return hipErrorInvalidValue;
   TMat pm;
   lagrange_matrix(c->nn, c->nodes, f->nn, f->nodes, pm.P);
+  InterpArrays arr{};
+  for (int i = 0; i < count; ++i) {
+    arr.nw[i] = new_c[i];
+    arr.old[i] = old_c[i];
+    arr.io[i] = inout_f[i];
+  }
   const long long work = (long long)batch * 3 * c->K;
-  hipLaunchKernelGGL(k_interp_add, dim3(nblocks(work, 256)), dim3(256), 0, s, new_c, old_c,
-                     inout_f, c->T, f->T, c->nn, f->nn, batch, pm);
+  hipLaunchKernelGGL(k_interp_add, dim3(nblocks(work, 256), count), dim3(256), 0, s, arr, c->T,
+                     f->T, c->nn, f->nn, batch, pm);
   return hipGetLastError();
+}
+
+hipError_t launch_interp_add(const pfsh_level* c, const pfsh_level* f, const double* new_c,
+                             const double* old_c, double* inout_f, int batch, hipStream_t s) {
+  return launch_interp_add3(c, f, 1, &new_c, &old_c, &inout_f, batch, s);
 }
 
 hipError_t launch_fas_tau(const pfsh_level* f, const pfsh_level* c, double dt, const double* fe_f,

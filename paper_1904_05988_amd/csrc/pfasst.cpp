@@ -163,9 +163,12 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     pending = defer;
   }
   // D) interpolate the coarse increments; new fine initial conditions
-  PF_TRY(launch_interp_add(x->c, x->f, x->thc, x->tthc, thf, B, s));
-  PF_TRY(launch_interp_add(x->c, x->f, x->fec, x->tfec, fef, B, s));
-  PF_TRY(launch_interp_add(x->c, x->f, x->fic, x->tfic, fif, B, s));
+  {
+    const double* nw[3] = {x->thc, x->fec, x->fic};
+    const double* od[3] = {x->tthc, x->tfec, x->tfic};
+    double* io[3] = {thf, fef, fif};
+    PF_TRY(launch_interp_add3(x->c, x->f, 3, nw, od, io, B, s));
+  }
   if (x->n_ts > 1)
     PF_TRY(launch_ic_correct(x->f, x->c, x->snap, z.n3kf, x->thc + 2 * (size_t)mem * z.stc, z.stc,
                              thf + 2 * (size_t)mem * z.stf, z.stf, B - mem, s));
@@ -242,9 +245,12 @@ hipError_t run_wavefront(pfsh_pfasst* x, double dt, double* thf, double* fef, do
     }
     // D) interpolate the coarse increments, new fine initial conditions, fine F
     //    at node 0 (on the level of the next iteration)
-    PF_TRY(launch_interp_add(x->c, x->f, x->thc + oc, x->tthc + oc, thf + of, nb, s));
-    PF_TRY(launch_interp_add(x->c, x->f, x->fec + oc, x->tfec + oc, fef + of, nb, s));
-    PF_TRY(launch_interp_add(x->c, x->f, x->fic + oc, x->tfic + oc, fif + of, nb, s));
+    {
+      const double* nw[3] = {x->thc + oc, x->fec + oc, x->fic + oc};
+      const double* od[3] = {x->tthc + oc, x->tfec + oc, x->tfic + oc};
+      double* io[3] = {thf + of, fef + of, fif + of};
+      PF_TRY(launch_interp_add3(x->c, x->f, 3, nw, od, io, nb, s));
+    }
     if (r_lo <= b_hi) {
       const int nr = (b_hi - r_lo + 1) * mem;
       PF_TRY(launch_ic_correct(x->f, x->c, fm_prev + (size_t)(r_lo - 1) * mem * 2 * z.n3kf, z.n3kf,

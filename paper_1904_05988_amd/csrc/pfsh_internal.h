@@ -217,6 +217,10 @@ hipError_t launch_restrict(const pfsh_level* f, const pfsh_level* c, const doubl
                            double* out_c, int batch, hipStream_t s);
 hipError_t launch_interp_add(const pfsh_level* c, const pfsh_level* f, const double* new_c,
                              const double* old_c, double* inout_f, int batch, hipStream_t s);
+// the same for `count` (1-3) array triples in one launch
+hipError_t launch_interp_add3(const pfsh_level* c, const pfsh_level* f, int count,
+                              const double* const* new_c, const double* const* old_c,
+                              double* const* inout_f, int batch, hipStream_t s);
 hipError_t launch_fas_tau(const pfsh_level* f, const pfsh_level* c, double dt, const double* fe_f,
                           const double* fi_f, const double* fe_c, const double* fi_c, double* tau,
                           int batch, hipStream_t s);
