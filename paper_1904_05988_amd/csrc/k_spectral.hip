@@ -227,10 +227,14 @@ template <typename R>
 __device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, int eoff, int m,
                                               int n, int T, double a, C2 out[3]) {
   const int np0 = npar(T, m, 0);
+  // degrees outside m..T+1 read 0; the load itself goes to degree m (in
+  // range) and is discarded, so no load sits behind a branch
   auto get = [&](int f, int nn) -> C2 {
-    if (nn < m || nn > T + 1) return {0.0, 0.0};
-    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + ((nn - m) & 1 ? np0 : 0) + ((nn - m) >> 1));
-    return {(double)p[0], (double)p[1]};
+    const bool in = nn >= m && nn <= T + 1;
+    const int q = in ? nn - m : 0;
+    const R* p = Yb + 2 * ((size_t)f * Kx + eoff + (q & 1 ? np0 : 0) + (q >> 1));
+    const double x = (double)p[0], y = (double)p[1];
+    return C2{in ? x : 0.0, in ? y : 0.0};
   };
   assemble_core(get, m, n, a, out);
 }
@@ -309,17 +313,48 @@ struct SrcPtrs {
 //  then b = S_node + dt sum_{j=1}^{node-1} (qE F_E^j + qI F_I^j) (new F), the
 //  implicit solve with beta = dt qI_{node,node}, Theta^node and
 //  F_I^node = L Theta^node, stored; returns Theta^node.
-template <int NN>
+// ND > 0 fixes the node at compile time (node_rt is then ignored): for a node
+// >= 2 every load of the mode (S and F_E, F_I of the earlier nodes, all three
+// variables) is issued before any arithmetic, one memory round trip instead of
+// one per term, and fe_prev (if given) holds F_E of node - 1 for the three
+// variables, already in registers.  Each term is fma(qE, F_E, qI F_I), added
+// in order j = 1, 2, ..., so both forms give the same bits.
+template <int NN, int ND = 0>
 __device__ __forceinline__ void node_update(double* __restrict__ th, double* __restrict__ fe,
                                             double* __restrict__ fi, const double* __restrict__ tau,
                                             double* __restrict__ S, const SrcPtrs& src, int K,
-                                            int b, int k, int n, int node, double dt,
-                                            const SdcMat& sm, const Phys& ph, C2 x[3]) {
+                                            int b, int k, int n, int node_rt, double dt,
+                                            const SdcMat& sm, const Phys& ph, C2 x[3],
+                                            const C2* fe_prev = nullptr) {
   constexpr int nn = NN, M = NN - 1;
+  const int node = ND > 0 ? ND : node_rt;
   const double lam = -(double)n * (n + 1) / (ph.a * ph.a);
   const double beta = dt * sm.QI[node * nn + node];
   const size_t base = (size_t)b * nn * 3 * K;
   C2 rhs[3];
+  if constexpr (ND >= 2) {
+    C2 E[3][ND], F[3][ND];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const size_t vk = (size_t)v * K + k;
+      rhs[v] = ld2(S + 2 * (((size_t)b * M + (ND - 1)) * 3 * K + vk));
+#pragma unroll
+      for (int j = 1; j < ND; ++j) {
+        const size_t o = base + (size_t)j * 3 * K + vk;
+        E[v][j] = (fe_prev && j == ND - 1) ? fe_prev[v] : ld2(fe + 2 * o);
+        F[v][j] = ld2(fi + 2 * o);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads above, all in flight
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int j = 1; j < ND; ++j) {
+        const double ce = dt * sm.QE[ND * nn + j], ci = dt * sm.QI[ND * nn + j];
+        rhs[v].x += fma(ce, E[v][j].x, ci * F[v][j].x);
+        rhs[v].y += fma(ce, E[v][j].y, ci * F[v][j].y);
+      }
+  } else
   for (int v = 0; v < 3; ++v) {
     const size_t vk = (size_t)v * K + k;
     C2 r;
@@ -329,6 +364,11 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
       for (int j = 0; j < nn; ++j) {
         E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
         I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
+      }
+      C2 tv[NN];   // tau of nodes 1..M, loaded together
+      if (tau) {
+#pragma unroll
+        for (int i = 1; i <= M; ++i) tv[i] = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
       }
       C2 t0;
       if (src.th) {   // node 0 received from src (state and F there), stored first
@@ -363,9 +403,8 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
         }
         C2 si = {t0.x + dt * sx, t0.y + dt * sy};
         if (tau) {
-          const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
-          si.x += tv.x;
-          si.y += tv.y;
+          si.x += tv[i].x;
+          si.y += tv[i].y;
         }
         if (i == 1)
           r = si;
@@ -374,13 +413,14 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
       }
     } else {
       r = ld2(S + 2 * (((size_t)b * M + (node - 1)) * 3 * K + vk));
-      for (int j = 1; j < node; ++j) {
+      auto term = [&](int j) {
         const size_t o = base + (size_t)j * 3 * K + vk;
         const C2 e = ld2(fe + 2 * o), f = ld2(fi + 2 * o);
         const double ce = dt * sm.QE[node * nn + j], ci = dt * sm.QI[node * nn + j];
-        r.x += ce * e.x + ci * f.x;
-        r.y += ce * e.y + ci * f.y;
-      }
+        r.x += fma(ce, e.x, ci * f.x);
+        r.y += fma(ce, e.y, ci * f.y);
+      };
+      for (int j = 1; j < node; ++j) term(j);
     }
     rhs[v] = r;
   }
@@ -404,8 +444,8 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
 // slice (order 0 and, for even T + 1, order (T + 1) / 2 stand alone).  The
 // (slice, order, degree) items of (a)-(b) are spread over all threads, (c)
 // takes one (order, degree) per thread.
-template <class Op, int NN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NN <= 5 ? 4 : 1)))
+template <class Op, int NN, int ND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NN <= 5 ? 4 : 1, ND > 1 ? 4 : 8)))
 void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
                                                    double* __restrict__ fi,
                                                    const double* __restrict__ tau,
@@ -431,14 +471,17 @@ void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
     const int m = first ? ma : mb, n = m + (first ? idx : idx - na);
     const int b = b0 + bb;
     const int k = spec_off(T, m) + n - m;
-    if (asm_node >= 0) {
-      C2 o[3];
+    // a compile-time node >= 2 always assembles F_E of node - 1 first
+    const int an = ND >= 2 ? ND - 1 : asm_node;
+    C2 o[3];
+    if (an >= 0) {
       assemble_mode(Y + (size_t)b * 5 * Kx * 2, Kx, ext_off(T, m), m, n, T, ph.a, o);
       const size_t base = (size_t)b * nn * 3 * K;
-      for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)asm_node * 3 + v) * K + k), o[v]);
+      for (int v = 0; v < 3; ++v) st2(fe + 2 * (base + ((size_t)an * 3 + v) * K + k), o[v]);
     }
     C2 x[3];
-    node_update<NN>(th, fe, fi, tau, S, src, K, b, k, n, node, dt, sm, ph, x);
+    node_update<NN, ND>(th, fe, fi, tau, S, src, K, b, k, n, node, dt, sm, ph, x,
+                        ND >= 2 ? o : nullptr);
     for (int v = 0; v < 3; ++v) sh[(bb * 3 + v) * L + idx] = x[v];
   }
   __syncthreads();
@@ -996,20 +1039,39 @@ hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double
     default: CALL(9); break;     \
   }
 
+template <class Op, int NN, int ND>
+static hipError_t sweep_step_nd(const pfsh_level* lv, int node, int asm_node, double dt,
+                                double* th, double* fe, double* fi, const double* tau, int batch,
+                                const StepSrc& src, hipStream_t s) {
+  const size_t shm = (size_t)2 * 3 * (lv->T + 1) * sizeof(C2);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN, ND>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  // order pairs (g, L - g): order 0, L/2 - 1 or (L-1)/2 pairs, and order L/2 for even L
+  hipLaunchKernelGGL((k_sweep_step<Op, NN, ND>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm,
+                     s, th, fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d,
+                     lv->T, lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
+                     SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});
+  return hipGetLastError();
+}
+
+// Up to 5 nodes the node is a template argument (one kernel per node; a node
+// >= 2 then assembles F_E of node - 1, the sweep's order), above that a
+// run-time argument.
 template <class Op, int NN>
 static hipError_t sweep_step_impl(const pfsh_level* lv, int node, int asm_node, double dt,
                                   double* th, double* fe, double* fi, const double* tau, int batch,
                                   const StepSrc& src, hipStream_t s) {
-  const size_t shm = (size_t)2 * 3 * (lv->T + 1) * sizeof(C2);
-  if (shm > 65536)
-    (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  // order pairs (g, L - g): order 0, L/2 - 1 or (L-1)/2 pairs, and order L/2 for even L
-  hipLaunchKernelGGL((k_sweep_step<Op, NN>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm, s, th,
-                     fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d, lv->T,
-                     lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
-                     SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});
-  return hipGetLastError();
+#define PFSH_ND(D) sweep_step_nd<Op, NN, D>(lv, node, asm_node, dt, th, fe, fi, tau, batch, src, s)
+  if constexpr (NN <= 5) {
+    if (node == 1) return PFSH_ND(1);
+    if (asm_node != node - 1) return PFSH_ND(0);
+    if (NN > 2 && node == 2) return PFSH_ND((NN > 2 ? 2 : 0));
+    if (NN > 3 && node == 3) return PFSH_ND((NN > 3 ? 3 : 0));
+    if (NN > 4 && node == 4) return PFSH_ND((NN > 4 ? 4 : 0));
+  }
+  return PFSH_ND(0);
+#undef PFSH_ND
 }
 
 template <class Op, int NN>
