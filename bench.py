@@ -117,8 +117,9 @@ def sweep_node_bytes(T, nn, B, rsz):
     """Algorithmic HBM bytes of one fused sweep-node launch, averaged over the
     nodes 1..M of a sweep: FP64 states of 3 K complex per slice read and written
     (node 1: Theta^0 and all F to form the old-iterate sums, S_2..S_M written;
-    node i: S_i, F of nodes 1..i-1 and the analysed products of node i-1 read,
-    F_E of node i-1 written), plus Theta^i and F_I^i and the synthesis operand."""
+    node i: S_i, F of nodes 1..i-1 but F_E of node i-1 (assembled in the same
+    kernel from the analysed products of node i-1, which are read) read, F_E of
+    node i-1 written), plus Theta^i and F_I^i and the synthesis operand."""
     M = nn - 1
     K = (T + 1) * (T + 2) // 2
     st = 3 * K * 16 * B                                   # one FP64 state array
@@ -130,7 +131,7 @@ def sweep_node_bytes(T, nn, B, rsz):
         if i == 1:
             tot += (1 + 2 * nn) * st + (M - 1) * st
         else:
-            tot += st + 2 * (i - 1) * st + y + st
+            tot += st + (2 * (i - 1) - 1) * st + y + st
         tot += 2 * st + x
     return tot / M
 
@@ -469,7 +470,7 @@ def main():
     # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counters of these kernel
     # versions (reads x2, writes x1 after calibration against a plain copy), FP32
     # fine level at T255 over 16 slices; the sweep node is averaged over nodes 1-4
-    measured = {("sweep_node", "fp32", 255, 16): 297.27e6, ("ring", "fp32", 255, 16): 114.56e6,
+    measured = {("sweep_node", "fp32", 255, 16): 280.71e6, ("ring", "fp32", 255, 16): 114.56e6,
                 ("leg_synth", "fp32", 255, 16): 104.35e6, ("leg_anal", "fp32", 255, 16): 119.73e6}
     if dom is not None:
         roof["traffic"] = measured.get((dom, args.mixed, Tf, B))   # HBM bytes per launch (measured)

@@ -365,11 +365,6 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
         E[j] = ld2(fe + 2 * (base + (size_t)j * 3 * K + vk));
         I[j] = ld2(fi + 2 * (base + (size_t)j * 3 * K + vk));
       }
-      C2 tv[NN];   // tau of nodes 1..M, loaded together
-      if (tau) {
-#pragma unroll
-        for (int i = 1; i <= M; ++i) tv[i] = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
-      }
       C2 t0;
       if (src.th) {   // node 0 received from src (state and F there), stored first
         const size_t so = 2 * ((size_t)b * src.stride + vk);
@@ -403,8 +398,9 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
         }
         C2 si = {t0.x + dt * sx, t0.y + dt * sy};
         if (tau) {
-          si.x += tv[i].x;
-          si.y += tv[i].y;
+          const C2 tv = ld2(tau + 2 * (base + (size_t)i * 3 * K + vk));
+          si.x += tv.x;
+          si.y += tv.y;
         }
         if (i == 1)
           r = si;
