@@ -19,7 +19,10 @@
 // one degree block per wave), never the order of a sum.  Operands are
 // pre-packed in MFMA lane order (tables at level creation, data by the
 // producing kernels), so each lane loads its fragment with one contiguous load;
-// the K loops (mfma_ops.h) run without branches, FP32 in two accumulation chains.
+// the analysis table of FP32 and FP64 levels is k-grouped (four or two
+// k-blocks of a lane in 16 bytes), since the rate of wave load instructions,
+// not bytes, bounds these contractions.  The K loops (mfma_ops.h) run without
+// branches, FP32 in two accumulation chains.
 #include "mfma_ops.h"
 
 namespace pfsh {
@@ -305,8 +308,11 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
                       8LL * CBa * 64, (long long)CBa * 64, 64, kb2, r1, c1, lane, acc00, acc01,
                       acc10, acc11);
   } else {
-    mma_loop<Op, PF>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
-                     (long long)CBa, kb2, r1, c1, lane, acc00, acc01, acc10, acc11);
+    // k-grouped table: PF groups of KG k-blocks in flight
+    constexpr int KG = KGroup<Op>::KG;
+    mma_loop_grp<Op, PF>(tab, G, q.tabA / KG + rb0, (long long)q.rbA,
+                         (long long)it.mp * kb2 * CBa + cb0, (long long)CBa, kb2 / KG, r1, c1,
+                         lane, acc00, acc01, acc10, acc11);
   }
   const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
   auto put = [&](const typename Op::C& acc, int rb, int cb) {
@@ -323,45 +329,6 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
   if (c1) put(acc01, rb0, cb0 + 1);
   if (r1) put(acc10, rb0 + 1, cb0);
   if (r1 && c1) put(acc11, rb0 + 1, cb0 + 1);
-}
-
-// One wave per workgroup with a 64-degree x 64-column tile (4x4 MFMA blocks):
-// the table rows of a degree tile are read once per 64 columns, the data
-// operand once per degree tile.
-template <class Op, int PF>
-__global__ __launch_bounds__(64) void k_leg_anal_t4(const void* __restrict__ tab,
-                                                   const void* __restrict__ G,
-                                                   typename Op::R* __restrict__ Y,
-                                                   const MPInfo* __restrict__ mpi,
-                                                   const WorkItem* __restrict__ items, int nitems,
-                                                   int nct, int kb2, int CBa, int CBn, int ncols,
-                                                   int Kx, int T) {
-  int item, ct;
-  if (!xcd_tile(nitems, nct, item, ct)) return;
-  const WorkItem it = items[item];
-  const MPInfo q = mpi[it.mp];
-  const int lane = threadIdx.x;
-  const int rb0 = it.tile * 4, cb0 = ct * 4;
-  const int nr = min(4, q.rbA - rb0), nc = min(4, CBn - cb0);
-  if (nr <= 0 || nc <= 0) return;
-  typename Op::C acc[4][4] = {};
-  mma_tile<Op, PF, 4, 4>(tab, G, q.tabA + rb0, (long long)q.rbA, (long long)it.mp * kb2 * CBa + cb0,
-                         (long long)CBa, kb2, nr, nc, lane, acc);
-  const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      if (r >= nr || cb >= nc) continue;
-      const int c = (cb0 + cb) * 16 + (lane & 15);
-      if (c >= ncols) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = (rb0 + r) * 16 + Op::row(lane, v);
-        if (i < q.np)
-          Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (typename Op::R)acc[r][cb][v];
-      }
-    }
 }
 
 static inline unsigned xcd_grid(int nitems, int nct) {
@@ -388,15 +355,6 @@ static hipError_t synth_t4_impl(const pfsh_level* lv, int ncols, int nf, hipStre
   return hipGetLastError();
 }
 
-template <class Op, int PF>
-static hipError_t anal_t4_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
-  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
-  hipLaunchKernelGGL((k_leg_anal_t4<Op, PF>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(64), 0, s,
-                     lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
-                     nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
-  return hipGetLastError();
-}
-
 template <class Op, int PF, int SHAPE>
 static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = SHAPE == 0 ? (CBn + 3) / 4 : (CBn + 1) / 2;
@@ -410,12 +368,13 @@ static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
 //   synthesis, prefetch depth of the K loop (t4: 4x4-block wave tiles):
 //     FP64 / FP32 4 2 8 t4-4 t4-2 4h (4h: LDS exchange in two row halves);
 //     BF16x3 2 4
-//   analysis, (prefetch depth, tile shape): FP64 / FP32 (4,0) (2,0) (8,0) (4,1)
-//     (8,1) (4,t4) (2,t4); BF16x3 (2,0) (4,0) (2,1) (4,1)
+//   analysis, (prefetch depth, tile shape): FP64 / FP32 (2,0) (1,0) (4,0) (2,1)
+//     (4,1), depth in 16-byte k-groups; BF16x3 (2,0) (4,0) (2,1) (4,1), depth
+//     in k-blocks of 32
 // None changes the order of any sum, so all variants give the same bits.
 int leg_variant_count(int op, int stage) {
   if (stage == TS_SYNTH) return op == OP_BF16X3 ? 2 : 6;
-  return op == OP_BF16X3 ? 4 : 7;
+  return op == OP_BF16X3 ? 4 : 5;
 }
 
 hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
@@ -452,13 +411,11 @@ static hipError_t anal_variant(const pfsh_level* lv, int v, int ncols, hipStream
     }
   } else {
     switch (v) {
-      case 1: return anal_impl<Op, 2, 0>(lv, ncols, s);
-      case 2: return anal_impl<Op, 8, 0>(lv, ncols, s);
-      case 3: return anal_impl<Op, 4, 1>(lv, ncols, s);
-      case 4: return anal_impl<Op, 8, 1>(lv, ncols, s);
-      case 5: return anal_t4_impl<Op, 4>(lv, ncols, s);
-      case 6: return anal_t4_impl<Op, 2>(lv, ncols, s);
-      default: return anal_impl<Op, 4, 0>(lv, ncols, s);
+      case 1: return anal_impl<Op, 1, 0>(lv, ncols, s);
+      case 2: return anal_impl<Op, 4, 0>(lv, ncols, s);
+      case 3: return anal_impl<Op, 2, 1>(lv, ncols, s);
+      case 4: return anal_impl<Op, 4, 1>(lv, ncols, s);
+      default: return anal_impl<Op, 2, 0>(lv, ncols, s);
     }
   }
 }

@@ -557,9 +557,10 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
       const int p = r < q0.rbA ? 0 : 1, rb = p ? r - q0.rbA : r;
       const MPInfo& q = p ? q1 : q0;
       typename Op::C acc = {}, d1 = {}, d2 = {}, d3 = {};
-      mma_loop<Op, PF>(tabA, G, q.tabA + rb, (long long)q.rbA,
-                       (long long)(2 * m + p) * kb2 * CBa + cb, (long long)CBa, kb2, false,
-                       false, lane, acc, d1, d2, d3);
+      constexpr int KG = KGroup<Op>::KG;   // k-grouped analysis table
+      mma_loop_grp<Op, PF / 2>(tabA, G, q.tabA / KG + rb, (long long)q.rbA,
+                               (long long)(2 * m + p) * kb2 * CBa + cb, (long long)CBa, kb2 / KG,
+                               false, false, lane, acc, d1, d2, d3);
       const int c = cb * 16 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {

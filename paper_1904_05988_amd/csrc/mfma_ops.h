@@ -17,6 +17,7 @@
 namespace pfsh {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
@@ -197,6 +198,120 @@ __device__ __forceinline__ void mma_loop_rc(const void* __restrict__ A, const vo
 
 // The 2x2 K loop with the edge flags taken once per wave.  Every argument but
 // the accumulators and `lane` must be uniform over the wave.
+// k-grouped A operand (the analysis table of FP32 and FP64 levels): KG
+// consecutive k-blocks of one lane are contiguous, 16 bytes, so one load
+// instruction brings a lane KG k-blocks.  The vector memory path issues about
+// as many wave loads per cycle for 16 bytes per lane as for 4, so this cuts the
+// table's load instructions by KG.  Element of k-block k, block t (stride S
+// blocks per k-block), lane l, in a region starting at block base:
+// kgroup_elem(base, S, k, t, l, KG) (pfsh_internal.h).  The data operand keeps
+// the plain block layout: its producer, the ring stage, writes one ring per
+// workgroup, and k-grouped it would write 4-byte pieces of 16-byte groups
+// shared by four workgroups (measured: ring stage 48 -> 77 us at T255 x 16).
+template <class Op>
+struct KGroup {
+  static constexpr int KG = Op::KIND == OP_BF16X3 ? 1 : 16 / (int)sizeof(typename Op::R);
+};
+
+template <class Op>
+struct GrpVec;
+template <>
+struct GrpVec<OpF32> {
+  typedef f4_t V;
+};
+template <>
+struct GrpVec<OpF64> {
+  typedef d2_t V;
+};
+
+// K loop of one wave's 2x2 blocks with a k-grouped A operand: A group-block
+// index ta (+astep per group of KG k-blocks), B plain blocks at tb (+bstep per
+// k-block), ng groups.  The MFMAs of a group run in k order, so every block
+// sees the k-blocks in the order (and FP32 chains) of mma_loop_rc: the same
+// bits.  Branch-free like mma_loop_rc.
+template <class Op, int PF, bool R1, bool C1>
+__device__ __forceinline__ void mma_loop_grp_rc(const void* __restrict__ A,
+                                                const void* __restrict__ B, long long ta,
+                                                long long astep, long long tb, long long bstep,
+                                                int ng, int lane, typename Op::C& acc00,
+                                                typename Op::C& acc01, typename Op::C& acc10,
+                                                typename Op::C& acc11) {
+  typedef typename GrpVec<Op>::V V;
+  constexpr int KG = KGroup<Op>::KG;
+  constexpr bool SPL = SplitAcc<Op>::value;
+  static_assert(!SPL || KG % 2 == 0, "two accumulation chains need an even group");
+  const V* Av = reinterpret_cast<const V*>(A);
+  ta = wave_uniform(ta);
+  tb = wave_uniform(tb);
+  astep = wave_uniform(astep);
+  bstep = wave_uniform(bstep);
+  ng = __builtin_amdgcn_readfirstlane(ng);
+  if (ng <= 0) return;
+  typename Op::C x00 = {}, x01 = {}, x10 = {}, x11 = {};   // odd k-blocks (SPL)
+  V a0[PF], a1[PF];
+  typename Op::A b0[PF][KG], b1[PF][KG];
+  auto load = [&](int s, long long g) {
+    a0[s] = Av[(ta + g * astep) * 64 + lane];
+    if (R1) a1[s] = Av[(ta + g * astep + 1) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < KG; ++e) {
+      const long long kb = tb + (g * KG + e) * bstep;
+      b0[s][e] = Op::load(B, kb, lane);
+      if (C1) b1[s][e] = Op::load(B, kb + 1, lane);
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < PF; ++s) load(s, s < ng ? s : ng - 1);
+  auto step = [&](int s) {
+#pragma unroll
+    for (int e = 0; e < KG; ++e) {
+      typename Op::C& c00 = (SPL && (e & 1)) ? x00 : acc00;
+      typename Op::C& c01 = (SPL && (e & 1)) ? x01 : acc01;
+      typename Op::C& c10 = (SPL && (e & 1)) ? x10 : acc10;
+      typename Op::C& c11 = (SPL && (e & 1)) ? x11 : acc11;
+      c00 = Op::mma(a0[s][e], b0[s][e], c00);
+      if (C1) c01 = Op::mma(a0[s][e], b1[s][e], c01);
+      if (R1) c10 = Op::mma(a1[s][e], b0[s][e], c10);
+      if (R1 && C1) c11 = Op::mma(a1[s][e], b1[s][e], c11);
+    }
+  };
+  int g0 = 0;
+  for (; g0 + PF <= ng; g0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      step(s);
+      const int gn = g0 + s + PF;
+      load(s, gn < ng ? gn : ng - 1);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s)
+    if (g0 + s < ng) step(s);
+  if constexpr (SPL) {
+    acc00 += x00;
+    acc01 += x01;
+    acc10 += x10;
+    acc11 += x11;
+  }
+}
+
+template <class Op, int PF>
+__device__ __forceinline__ void mma_loop_grp(const void* __restrict__ A,
+                                             const void* __restrict__ B, long long ta,
+                                             long long astep, long long tb, long long bstep,
+                                             int ng, bool r1, bool c1, int lane,
+                                             typename Op::C& acc00, typename Op::C& acc01,
+                                             typename Op::C& acc10, typename Op::C& acc11) {
+  if (r1 && c1)
+    mma_loop_grp_rc<Op, PF, true, true>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+  else if (r1)
+    mma_loop_grp_rc<Op, PF, true, false>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+  else if (c1)
+    mma_loop_grp_rc<Op, PF, false, true>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+  else
+    mma_loop_grp_rc<Op, PF, false, false>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+}
+
 template <class Op, int PF>
 __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void* __restrict__ B,
                                          long long ta, long long astep, long long tb,

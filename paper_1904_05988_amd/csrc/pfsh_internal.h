@@ -45,6 +45,17 @@ __host__ __device__ inline int op_lane(int op, int r, int k) {
 }
 __host__ __device__ inline int op_elem(int op, int k) { return op == OP_BF16X3 ? (k & 7) : 0; }
 
+// k-blocks per 16-byte group of the analysis table: 4 FP32, 2 FP64, 1 (plain
+// blocks) BF16x3; element of k-block k, block t (stride S blocks per k-block),
+// lane l of a region that starts at block base (a multiple of KG).
+__host__ __device__ inline int kgroup_of(int op) {
+  return op == OP_BF16X3 ? 1 : (op == OP_F64 ? 2 : 4);
+}
+__host__ __device__ inline long long kgroup_elem(long long base, long long S, long long k,
+                                                 long long t, int lane, int KG) {
+  return base * 64 + (((k / KG) * S + t) * 64 + lane) * KG + k % KG;
+}
+
 // Per-(m, p) bookkeeping of the packed tables and operands (index mp = 2m+p).
 struct MPInfo {
   int m, p, np;       // order, parity, number of degrees

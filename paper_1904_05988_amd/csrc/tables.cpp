@@ -198,11 +198,20 @@ void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<
             long long blk = q.tabS + (long long)(i / KB) * lv->RB + j / 16;
             put(op, tabS.data(), blk, op_lane(op, j % 16, i % KB), op_elem(op, i % KB), v);
           }
-          // analysis: rows = degrees i, k = rings j
+          // analysis: rows = degrees i, k = rings j; FP32 / FP64 in k-groups
           {
             int KB = lv->KB;
-            long long blk = q.tabA + (long long)(j / KB) * q.rbA + i / 16;
-            put(op, tabA.data(), blk, op_lane(op, i % 16, j % KB), op_elem(op, j % KB), v);
+            if (op == OP_BF16X3) {
+              long long blk = q.tabA + (long long)(j / KB) * q.rbA + i / 16;
+              put(op, tabA.data(), blk, op_lane(op, i % 16, j % KB), op_elem(op, j % KB), v);
+            } else {
+              const long long e = kgroup_elem(q.tabA, q.rbA, j / KB, i / 16,
+                                              op_lane(op, i % 16, j % KB), kgroup_of(op));
+              if (op == OP_F64)
+                reinterpret_cast<double*>(tabA.data())[e] = v;
+              else
+                reinterpret_cast<float*>(tabA.data())[e] = (float)v;
+            }
           }
         }
       }
