@@ -471,7 +471,7 @@ def main():
     # versions (reads x2, writes x1 after calibration against a plain copy), FP32
     # fine level at T255 over 16 slices; the sweep node is averaged over nodes 1-4
     measured = {("sweep_node", "fp32", 255, 16): 280.71e6, ("ring", "fp32", 255, 16): 114.56e6,
-                ("leg_synth", "fp32", 255, 16): 104.35e6, ("leg_anal", "fp32", 255, 16): 119.73e6}
+                ("leg_synth", "fp32", 255, 16): 104.35e6, ("leg_anal", "fp32", 255, 16): 160.33e6}
     if dom is not None:
         roof["traffic"] = measured.get((dom, args.mixed, Tf, B))   # HBM bytes per launch (measured)
         roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
