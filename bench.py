@@ -469,11 +469,20 @@ def main():
         roof["frac"] = roof["achieved"] / roof["peak"]
     # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counters of these kernel
     # versions (reads x2, writes x1 after calibration against a plain copy), FP32
-    # fine level at T255 over 16 slices; the sweep node is averaged over nodes 1-4
-    measured = {("sweep_node", "fp32", 255, 16): 280.71e6, ("ring", "fp32", 255, 16): 114.56e6,
-                ("leg_synth", "fp32", 255, 16): 104.35e6, ("leg_anal", "fp32", 255, 16): 160.33e6}
+    # fine level at T255 over 16 slices, per tuner variant (the tuner may keep
+    # another one from run to run: then none); the sweep node is averaged over
+    # nodes 1-4
+    measured = {("sweep_node", "fp32", 255, 16, None): 280.71e6,
+                ("ring", "fp32", 255, 16, 0): 114.56e6,
+                ("leg_synth", "fp32", 255, 16, 0): 104.35e6,
+                ("leg_synth", "fp32", 255, 16, 3): 98.77e6,
+                ("leg_anal", "fp32", 255, 16, 0): 160.33e6,
+                ("leg_anal", "fp32", 255, 16, 6): 117.82e6}
+    stage_of = {"leg_synth": "synth", "leg_anal": "anal", "ring": "ring"}
     if dom is not None:
-        roof["traffic"] = measured.get((dom, args.mixed, Tf, B))   # HBM bytes per launch (measured)
+        var = rmx["tuned"].get("fine", {}).get(B, {}).get(stage_of.get(dom)) if dom in stage_of else None
+        roof["traffic"] = measured.get((dom, args.mixed, Tf, B, var))   # HBM bytes per launch (measured)
+        roof["variant"] = var
         roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
         roof["kernel"] = dom
         roof["launches"] = n

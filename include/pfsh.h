@@ -213,9 +213,10 @@ pfsh_status pfsh_profile_read_batch(pfsh_level* level, int kernel, int batch, in
  *            wave; 4 with the LDS exchange in two row halves; BF16x3: 2, 4);
  *   stage 1, Legendre analysis: (prefetch depth, tile shape), shape 0 = 64
  *            degrees x 64 columns per workgroup, 1 = 64 x 32 with one degree
- *            block per wave (FP64 / FP32, depth in 16-byte groups of the
- *            table, 4 or 2 k-blocks each: (2,0) (1,0) (4,0) (2,1) (4,1);
- *            BF16x3, depth in k-blocks: (2,0) (4,0) (2,1) (4,1));
+ *            block per wave, tall = 64 x 64 with 64 x 32 per wave (FP64 /
+ *            FP32, depth in 16-byte groups of the table, 4 or 2 k-blocks
+ *            each: (2,0) (1,0) (4,0) (2,1) (4,1) (1,tall) (2,tall); BF16x3,
+ *            depth in k-blocks: (2,0) (4,0) (2,1) (4,1));
  *   stage 2, ring FFTs + products of the RHS: largest radix 16, 8, 4 with
  *            256 threads per workgroup, radix 16 with 512 threads;
  *   stage 3, sweep path for batches of 1-2 slices on FP64 / FP32 levels:

@@ -331,6 +331,62 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
   if (r1 && c1) put(acc11, rb0 + 1, cb0 + 1);
 }
 
+// Tall wave tiles (FP32 / FP64): one workgroup of 2 waves per item (4 degree
+// blocks) and tile of 4 column blocks, each wave 4 x 2 blocks; the items and
+// column tiles of k_leg_anal's shape 0.  With the k-grouped table, the data
+// operand's loads dominate, and a taller tile shares each of them among 4
+// degree blocks.
+template <class Op, int PF>
+__global__ __launch_bounds__(128) void k_leg_anal_tall(const void* __restrict__ tab,
+                                                      const void* __restrict__ G,
+                                                      typename Op::R* __restrict__ Y,
+                                                      const MPInfo* __restrict__ mpi,
+                                                      const WorkItem* __restrict__ items,
+                                                      int nitems, int nct, int kb2, int CBa,
+                                                      int CBn, int ncols, int Kx, int T) {
+  int item, ct;
+  if (!xcd_tile(nitems, nct, item, ct)) return;
+  const WorkItem it = items[item];
+  const MPInfo q = mpi[it.mp];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb0 = it.tile * 4, cb0 = ct * 4 + wave * 2;
+  if (rb0 >= q.rbA || cb0 >= CBn) return;
+  const int nr = min(4, q.rbA - rb0);
+  const bool c1 = cb0 + 1 < CBn;
+  constexpr int KG = KGroup<Op>::KG;
+  typename Op::C acc[4][2] = {};
+  const long long ta = q.tabA / KG + rb0, tb = (long long)it.mp * kb2 * CBa + cb0;
+#define PFSH_TALL(N, C)                                                                        \
+  mma_loop_grp_tall<Op, PF, N, C>(tab, G, ta, (long long)q.rbA, tb, (long long)CBa, kb2 / KG, \
+                                  lane, acc)
+  switch (__builtin_amdgcn_readfirstlane(nr) * 2 + (c1 ? 1 : 0)) {
+    case 2: PFSH_TALL(1, false); break;
+    case 3: PFSH_TALL(1, true); break;
+    case 4: PFSH_TALL(2, false); break;
+    case 5: PFSH_TALL(2, true); break;
+    case 6: PFSH_TALL(3, false); break;
+    case 7: PFSH_TALL(3, true); break;
+    case 8: PFSH_TALL(4, false); break;
+    default: PFSH_TALL(4, true); break;
+  }
+#undef PFSH_TALL
+  const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      if (r >= nr || (cc == 1 && !c1)) continue;
+      const int c = (cb0 + cc) * 16 + (lane & 15);
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (rb0 + r) * 16 + Op::row(lane, v);
+        if (i < q.np)
+          Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (typename Op::R)acc[r][cc][v];
+      }
+    }
+}
+
 static inline unsigned xcd_grid(int nitems, int nct) {
   return (unsigned)(((nitems + 7) / 8) * 8 * nct);
 }
@@ -355,6 +411,15 @@ static hipError_t synth_t4_impl(const pfsh_level* lv, int ncols, int nf, hipStre
   return hipGetLastError();
 }
 
+template <class Op, int PF>
+static hipError_t anal_tall_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
+  hipLaunchKernelGGL((k_leg_anal_tall<Op, PF>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(128), 0, s,
+                     lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
+                     nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
+  return hipGetLastError();
+}
+
 template <class Op, int PF, int SHAPE>
 static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = SHAPE == 0 ? (CBn + 3) / 4 : (CBn + 1) / 2;
@@ -369,12 +434,12 @@ static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
 //     FP64 / FP32 4 2 8 t4-4 t4-2 4h (4h: LDS exchange in two row halves);
 //     BF16x3 2 4
 //   analysis, (prefetch depth, tile shape): FP64 / FP32 (2,0) (1,0) (4,0) (2,1)
-//     (4,1), depth in 16-byte k-groups; BF16x3 (2,0) (4,0) (2,1) (4,1), depth
-//     in k-blocks of 32
+//     (4,1) (1,tall) (2,tall), depth in 16-byte k-groups; BF16x3 (2,0) (4,0)
+//     (2,1) (4,1), depth in k-blocks of 32
 // None changes the order of any sum, so all variants give the same bits.
 int leg_variant_count(int op, int stage) {
   if (stage == TS_SYNTH) return op == OP_BF16X3 ? 2 : 6;
-  return op == OP_BF16X3 ? 4 : 5;
+  return op == OP_BF16X3 ? 4 : 7;
 }
 
 hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
@@ -415,6 +480,8 @@ static hipError_t anal_variant(const pfsh_level* lv, int v, int ncols, hipStream
       case 2: return anal_impl<Op, 4, 0>(lv, ncols, s);
       case 3: return anal_impl<Op, 2, 1>(lv, ncols, s);
       case 4: return anal_impl<Op, 4, 1>(lv, ncols, s);
+      case 5: return anal_tall_impl<Op, 1>(lv, ncols, s);
+      case 6: return anal_tall_impl<Op, 2>(lv, ncols, s);
       default: return anal_impl<Op, 2, 0>(lv, ncols, s);
     }
   }

@@ -312,6 +312,75 @@ __device__ __forceinline__ void mma_loop_grp(const void* __restrict__ A,
     mma_loop_grp_rc<Op, PF, false, false>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
 }
 
+// K loop of one wave's NR x 2 blocks (NR = 1..4 degree blocks, C1: second
+// column block present) with a k-grouped A operand, as mma_loop_grp_rc: the
+// data operand is loaded once per k-block and column for NR row blocks, so a
+// taller tile needs fewer load instructions per MFMA (4 x 2: 12 loads per 32
+// MFMAs against 10 per 16 for 2 x 2).  Same k order and chains: same bits.
+template <class Op, int PF, int NR, bool C1>
+__device__ __forceinline__ void mma_loop_grp_tall(const void* __restrict__ A,
+                                                  const void* __restrict__ B, long long ta,
+                                                  long long astep, long long tb, long long bstep,
+                                                  int ng, int lane, typename Op::C (&acc)[4][2]) {
+  typedef typename GrpVec<Op>::V V;
+  constexpr int KG = KGroup<Op>::KG;
+  constexpr bool SPL = SplitAcc<Op>::value;
+  const V* Av = reinterpret_cast<const V*>(A);
+  ta = wave_uniform(ta);
+  tb = wave_uniform(tb);
+  astep = wave_uniform(astep);
+  bstep = wave_uniform(bstep);
+  ng = __builtin_amdgcn_readfirstlane(ng);
+  if (ng <= 0) return;
+  typename Op::C x[NR][2] = {};   // odd k-blocks (SPL)
+  V a[PF][NR];
+  typename Op::A b[PF][KG][2];
+  auto load = [&](int s, long long g) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[s][r] = Av[(ta + g * astep + r) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < KG; ++e) {
+      const long long kb = tb + (g * KG + e) * bstep;
+      b[s][e][0] = Op::load(B, kb, lane);
+      if (C1) b[s][e][1] = Op::load(B, kb + 1, lane);
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < PF; ++s) load(s, s < ng ? s : ng - 1);
+  auto step = [&](int s) {
+#pragma unroll
+    for (int e = 0; e < KG; ++e)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        typename Op::C& c0 = (SPL && (e & 1)) ? x[r][0] : acc[r][0];
+        c0 = Op::mma(a[s][r][e], b[s][e][0], c0);
+        if (C1) {
+          typename Op::C& c1 = (SPL && (e & 1)) ? x[r][1] : acc[r][1];
+          c1 = Op::mma(a[s][r][e], b[s][e][1], c1);
+        }
+      }
+  };
+  int g0 = 0;
+  for (; g0 + PF <= ng; g0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      step(s);
+      const int gn = g0 + s + PF;
+      load(s, gn < ng ? gn : ng - 1);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s)
+    if (g0 + s < ng) step(s);
+  if constexpr (SPL) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      acc[r][0] += x[r][0];
+      if (C1) acc[r][1] += x[r][1];
+    }
+  }
+}
+
 template <class Op, int PF>
 __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void* __restrict__ B,
                                          long long ta, long long astep, long long tb,
