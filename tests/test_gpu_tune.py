@@ -21,7 +21,7 @@ def _rhs(gl, x):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 3), (63, 96, 192, 13)])
+@pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 3), (63, 96, 192, 13), (127, 192, 384, 16)])
 def test_legendre_variants_are_bitwise_equal(prec, T, nlat, nlon, B):
     gl = pfsh.Level(T, nlat, nlon, 3, max_batch=B, precision=prec)
     x = to_dev(seeded(T, range(B)))
