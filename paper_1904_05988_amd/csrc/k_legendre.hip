@@ -93,9 +93,18 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
     // small terms are summed before the large low-degree ones
     const MPInfo q = mpi[2 * m + p];
     const long long last = q.kbS - 1;
-    mma_loop<Op, PF>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
-                     q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, r1, c1, lane, acc[0],
-                     acc[1], acc[2], acc[3]);
+    constexpr int KG = KGroup<Op>::KG;
+    if constexpr (KG > 1) {
+      // table k-grouped from the highest k-block down: (PF + KG - 1) / KG groups ahead
+      mma_loop_grp<Op, (PF + KG - 1) / KG>(tab, X, q.tabS / KG + rb0, (long long)RB,
+                                           q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS / KG,
+                                           q.kbS % KG, r1, c1, lane, acc[0], acc[1], acc[2],
+                                           acc[3]);
+    } else {
+      mma_loop<Op, PF>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
+                       q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, r1, c1, lane, acc[0],
+                       acc[1], acc[2], acc[3]);
+    }
   }
   // HS = 32: one exchange of the whole tile; HS = 16: two rounds of one row
   // block each (half the LDS, so more workgroups fit on a CU)
@@ -159,8 +168,10 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_t4(const void* __restrict
   if (m <= T) {
     const MPInfo q = mpi[2 * m + p];
     const long long last = q.kbS - 1;
-    mma_tile<Op, PF, 4, 4>(tab, X, q.tabS + rb0 + last * RB, -(long long)RB,
-                           q.xS + cb0 + last * CBs, -(long long)CBs, q.kbS, nr, nc, lane, acc);
+    constexpr int KG = KGroup<Op>::KG;
+    mma_tile_grp<Op, (PF + KG - 1) / KG, 4, 4>(tab, X, q.tabS / KG + rb0, (long long)RB,
+                                               q.xS + cb0 + last * CBs, -(long long)CBs,
+                                               q.kbS / KG, q.kbS % KG, nr, nc, lane, acc);
   }
 #pragma unroll
   for (int qd = 0; qd < 4; ++qd) {
@@ -311,8 +322,8 @@ __global__ __launch_bounds__(256) void k_leg_anal(const void* __restrict__ tab,
     // k-grouped table: PF groups of KG k-blocks in flight
     constexpr int KG = KGroup<Op>::KG;
     mma_loop_grp<Op, PF>(tab, G, q.tabA / KG + rb0, (long long)q.rbA,
-                         (long long)it.mp * kb2 * CBa + cb0, (long long)CBa, kb2 / KG, r1, c1,
-                         lane, acc00, acc01, acc10, acc11);
+                         (long long)it.mp * kb2 * CBa + cb0, (long long)CBa, kb2 / KG, 0, r1,
+                         c1, lane, acc00, acc01, acc10, acc11);
   }
   const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
   auto put = [&](const typename Op::C& acc, int rb, int cb) {

@@ -560,7 +560,7 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
       constexpr int KG = KGroup<Op>::KG;   // k-grouped analysis table
       mma_loop_grp<Op, PF / 2>(tabA, G, q.tabA / KG + rb, (long long)q.rbA,
                                (long long)(2 * m + p) * kb2 * CBa + cb, (long long)CBa, kb2 / KG,
-                               false, false, lane, acc, d1, d2, d3);
+                               0, false, false, lane, acc, d1, d2, d3);
       const int c = cb * 16 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -621,8 +621,10 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
     if (q.kbS == 0) continue;
     const long long last = q.kbS - 1;
     typename Op::C acc = {}, d1 = {}, d2 = {}, d3 = {};
-    mma_loop<Op, PF>(tabS, Xl, q.tabS + rb + last * RB, -(long long)RB,
-                     (long long)p * kbmax + last, -1LL, q.kbS, false, false, lane, acc, d1, d2, d3);
+    constexpr int KG = KGroup<Op>::KG;   // table k-grouped from the highest k-block down
+    mma_loop_grp<Op, (PF + KG - 1) / KG>(tabS, Xl, q.tabS / KG + rb, (long long)RB,
+                                         (long long)p * kbmax + last, -1LL, q.kbS / KG,
+                                         q.kbS % KG, false, false, lane, acc, d1, d2, d3);
     const int c = lane & 15;
     if (c < 8 * nsl) {
       const int b = c >> 3, f = (c & 7) >> 1;

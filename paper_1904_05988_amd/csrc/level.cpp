@@ -115,7 +115,10 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
       q.tabS = tS;
       q.tabA = tA;
       q.xS = xS;
-      tS += (long long)q.kbS * lv->RB;
+      {   // synthesis table region: k-blocks padded to whole 16-byte groups
+        const int kg = kgroup_of(lv->op);
+        tS += (long long)((q.kbS + kg - 1) / kg * kg) * lv->RB;
+      }
       tA += (long long)lv->kb2 * q.rbA;
       xS += (long long)q.kbS * lv->CBs;
     }

@@ -226,14 +226,17 @@ struct GrpVec<OpF64> {
 
 // K loop of one wave's 2x2 blocks with a k-grouped A operand: A group-block
 // index ta (+astep per group of KG k-blocks), B plain blocks at tb (+bstep per
-// k-block), ng groups.  The MFMAs of a group run in k order, so every block
-// sees the k-blocks in the order (and FP32 chains) of mma_loop_rc: the same
-// bits.  Branch-free like mma_loop_rc.
+// k-block, negative for the synthesis, which runs from the highest k-block
+// down and groups its table in that order), ng whole groups, then rem (0..KG-1)
+// k-blocks of a last, padded group.  The MFMAs of a group run in k order, so
+// every block sees the k-blocks in the order (and FP32 chains) of
+// mma_loop_rc: the same bits.  Branch-free like mma_loop_rc but for the rem
+// tail.
 template <class Op, int PF, bool R1, bool C1>
 __device__ __forceinline__ void mma_loop_grp_rc(const void* __restrict__ A,
                                                 const void* __restrict__ B, long long ta,
                                                 long long astep, long long tb, long long bstep,
-                                                int ng, int lane, typename Op::C& acc00,
+                                                int ng, int rem, int lane, typename Op::C& acc00,
                                                 typename Op::C& acc01, typename Op::C& acc10,
                                                 typename Op::C& acc11) {
   typedef typename GrpVec<Op>::V V;
@@ -246,7 +249,7 @@ __device__ __forceinline__ void mma_loop_grp_rc(const void* __restrict__ A,
   astep = wave_uniform(astep);
   bstep = wave_uniform(bstep);
   ng = __builtin_amdgcn_readfirstlane(ng);
-  if (ng <= 0) return;
+  rem = __builtin_amdgcn_readfirstlane(rem);
   typename Op::C x00 = {}, x01 = {}, x10 = {}, x11 = {};   // odd k-blocks (SPL)
   V a0[PF], a1[PF];
   typename Op::A b0[PF][KG], b1[PF][KG];
@@ -260,33 +263,51 @@ __device__ __forceinline__ void mma_loop_grp_rc(const void* __restrict__ A,
       if (C1) b1[s][e] = Op::load(B, kb + 1, lane);
     }
   };
-#pragma unroll
-  for (int s = 0; s < PF; ++s) load(s, s < ng ? s : ng - 1);
+  auto mma_e = [&](int s, int e) {
+    typename Op::C& c00 = (SPL && (e & 1)) ? x00 : acc00;
+    typename Op::C& c01 = (SPL && (e & 1)) ? x01 : acc01;
+    typename Op::C& c10 = (SPL && (e & 1)) ? x10 : acc10;
+    typename Op::C& c11 = (SPL && (e & 1)) ? x11 : acc11;
+    c00 = Op::mma(a0[s][e], b0[s][e], c00);
+    if (C1) c01 = Op::mma(a0[s][e], b1[s][e], c01);
+    if (R1) c10 = Op::mma(a1[s][e], b0[s][e], c10);
+    if (R1 && C1) c11 = Op::mma(a1[s][e], b1[s][e], c11);
+  };
   auto step = [&](int s) {
 #pragma unroll
-    for (int e = 0; e < KG; ++e) {
-      typename Op::C& c00 = (SPL && (e & 1)) ? x00 : acc00;
-      typename Op::C& c01 = (SPL && (e & 1)) ? x01 : acc01;
-      typename Op::C& c10 = (SPL && (e & 1)) ? x10 : acc10;
-      typename Op::C& c11 = (SPL && (e & 1)) ? x11 : acc11;
-      c00 = Op::mma(a0[s][e], b0[s][e], c00);
-      if (C1) c01 = Op::mma(a0[s][e], b1[s][e], c01);
-      if (R1) c10 = Op::mma(a1[s][e], b0[s][e], c10);
-      if (R1 && C1) c11 = Op::mma(a1[s][e], b1[s][e], c11);
-    }
+    for (int e = 0; e < KG; ++e) mma_e(s, e);
   };
-  int g0 = 0;
-  for (; g0 + PF <= ng; g0 += PF) {
+  if (ng > 0) {
 #pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      step(s);
-      const int gn = g0 + s + PF;
-      load(s, gn < ng ? gn : ng - 1);
+    for (int s = 0; s < PF; ++s) load(s, s < ng ? s : ng - 1);
+    int g0 = 0;
+    for (; g0 + PF <= ng; g0 += PF) {
+#pragma unroll
+      for (int s = 0; s < PF; ++s) {
+        step(s);
+        const int gn = g0 + s + PF;
+        load(s, gn < ng ? gn : ng - 1);
+      }
     }
-  }
 #pragma unroll
-  for (int s = 0; s < PF - 1; ++s)
-    if (g0 + s < ng) step(s);
+    for (int s = 0; s < PF - 1; ++s)
+      if (g0 + s < ng) step(s);
+  }
+  if (rem > 0) {   // k-blocks g KG + e, e < rem, of the last group
+    a0[0] = Av[(ta + ng * astep) * 64 + lane];
+    if (R1) a1[0] = Av[(ta + ng * astep + 1) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < KG - 1; ++e) {
+      if (e < rem) {
+        const long long kb = tb + ((long long)ng * KG + e) * bstep;
+        b0[0][e] = Op::load(B, kb, lane);
+        if (C1) b1[0][e] = Op::load(B, kb + 1, lane);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < KG - 1; ++e)
+      if (e < rem) mma_e(0, e);
+  }
   if constexpr (SPL) {
     acc00 += x00;
     acc01 += x01;
@@ -299,17 +320,108 @@ template <class Op, int PF>
 __device__ __forceinline__ void mma_loop_grp(const void* __restrict__ A,
                                              const void* __restrict__ B, long long ta,
                                              long long astep, long long tb, long long bstep,
-                                             int ng, bool r1, bool c1, int lane,
+                                             int ng, int rem, bool r1, bool c1, int lane,
                                              typename Op::C& acc00, typename Op::C& acc01,
                                              typename Op::C& acc10, typename Op::C& acc11) {
   if (r1 && c1)
-    mma_loop_grp_rc<Op, PF, true, true>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+    mma_loop_grp_rc<Op, PF, true, true>(A, B, ta, astep, tb, bstep, ng, rem, lane, acc00, acc01, acc10, acc11);
   else if (r1)
-    mma_loop_grp_rc<Op, PF, true, false>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+    mma_loop_grp_rc<Op, PF, true, false>(A, B, ta, astep, tb, bstep, ng, rem, lane, acc00, acc01, acc10, acc11);
   else if (c1)
-    mma_loop_grp_rc<Op, PF, false, true>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+    mma_loop_grp_rc<Op, PF, false, true>(A, B, ta, astep, tb, bstep, ng, rem, lane, acc00, acc01, acc10, acc11);
   else
-    mma_loop_grp_rc<Op, PF, false, false>(A, B, ta, astep, tb, bstep, ng, lane, acc00, acc01, acc10, acc11);
+    mma_loop_grp_rc<Op, PF, false, false>(A, B, ta, astep, tb, bstep, ng, rem, lane, acc00, acc01, acc10, acc11);
+}
+
+// K loop of one wave's RT x CT blocks with a k-grouped A operand (the
+// synthesis table, grouped from its highest k-block down): A group-blocks ta +
+// r (+astep per group), B plain blocks tb + c (+bstep per k-block), ng whole
+// groups then rem k-blocks of a padded last group.  Rows r >= nr and columns
+// c >= nc repeat the last valid one (their results are not stored), so the
+// loop has no branches; each valid block sees the k-blocks in the order and
+// FP32 chains of mma_tile: the same bits.
+template <class Op, int PF, int RT, int CT>
+__device__ __forceinline__ void mma_tile_grp(const void* __restrict__ A, const void* __restrict__ B,
+                                             long long ta, long long astep, long long tb,
+                                             long long bstep, int ng, int rem, int nr, int nc,
+                                             int lane, typename Op::C (&acc)[RT][CT]) {
+  typedef typename GrpVec<Op>::V V;
+  constexpr int KG = KGroup<Op>::KG;
+  constexpr bool SPL = SplitAcc<Op>::value;
+  const V* Av = reinterpret_cast<const V*>(A);
+  ta = wave_uniform(ta);
+  tb = wave_uniform(tb);
+  astep = wave_uniform(astep);
+  bstep = wave_uniform(bstep);
+  ng = __builtin_amdgcn_readfirstlane(ng);
+  rem = __builtin_amdgcn_readfirstlane(rem);
+  nr = __builtin_amdgcn_readfirstlane(nr);
+  nc = __builtin_amdgcn_readfirstlane(nc);
+  int ro[RT], co[CT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) ro[r] = r < nr ? r : nr - 1;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) co[c] = c < nc ? c : nc - 1;
+  typename Op::C x[RT][CT] = {};   // odd k-blocks (SPL)
+  V a[PF][RT];
+  typename Op::A b[PF][KG][CT];
+  auto load = [&](int s, long long g) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[s][r] = Av[(ta + g * astep + ro[r]) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < KG; ++e)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[s][e][c] = Op::load(B, tb + (g * KG + e) * bstep + co[c], lane);
+  };
+  auto mma_e = [&](int s, int e) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        typename Op::C& t = (SPL && (e & 1)) ? x[r][c] : acc[r][c];
+        t = Op::mma(a[s][r][e], b[s][e][c], t);
+      }
+  };
+  if (ng > 0) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) load(s, s < ng ? s : ng - 1);
+    int g0 = 0;
+    for (; g0 + PF <= ng; g0 += PF) {
+#pragma unroll
+      for (int s = 0; s < PF; ++s) {
+#pragma unroll
+        for (int e = 0; e < KG; ++e) mma_e(s, e);
+        const int gn = g0 + s + PF;
+        load(s, gn < ng ? gn : ng - 1);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < PF - 1; ++s)
+      if (g0 + s < ng) {
+#pragma unroll
+        for (int e = 0; e < KG; ++e) mma_e(s, e);
+      }
+  }
+  if (rem > 0) {   // k-blocks ng KG + e, e < rem, of the last group
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[0][r] = Av[(ta + ng * astep + ro[r]) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < KG - 1; ++e)
+      if (e < rem) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          b[0][e][c] = Op::load(B, tb + ((long long)ng * KG + e) * bstep + co[c], lane);
+      }
+#pragma unroll
+    for (int e = 0; e < KG - 1; ++e)
+      if (e < rem) mma_e(0, e);
+  }
+  if constexpr (SPL) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[r][c] += x[r][c];
+  }
 }
 
 // K loop of one wave's NR x 2 blocks (NR = 1..4 degree blocks, C1: second

@@ -160,7 +160,8 @@ void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<
   const size_t bb = (size_t)op_block_bytes(op);
   long long nS = 0, nA = 0;
   for (auto& q : lv->mp) {
-    nS = std::max(nS, q.tabS + (long long)q.kbS * lv->RB);
+    const int kg = kgroup_of(op);
+    nS = std::max(nS, q.tabS + (long long)((q.kbS + kg - 1) / kg * kg) * lv->RB);
     nA = std::max(nA, q.tabA + (long long)lv->kb2 * q.rbA);
   }
   tabS.assign((size_t)nS * bb, 0);
@@ -192,11 +193,22 @@ void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<
         for (int i = 0; i < q.np; ++i) {
           double v = (double)row[p + 2 * i];
           if (std::fabs(v) < 1e-290) v = 0.0;
-          // synthesis: rows = rings j, k = i
+          // synthesis: rows = rings j, k = i; FP32 / FP64 in k-groups counted
+          // from the highest k-block down (the order the contraction runs)
           {
             int KB = lv->KB;
-            long long blk = q.tabS + (long long)(i / KB) * lv->RB + j / 16;
-            put(op, tabS.data(), blk, op_lane(op, j % 16, i % KB), op_elem(op, i % KB), v);
+            if (op == OP_BF16X3) {
+              long long blk = q.tabS + (long long)(i / KB) * lv->RB + j / 16;
+              put(op, tabS.data(), blk, op_lane(op, j % 16, i % KB), op_elem(op, i % KB), v);
+            } else {
+              const long long r = (long long)(q.kbS - 1) - i / KB;   // descending k-block
+              const long long e = kgroup_elem(q.tabS, lv->RB, r, j / 16,
+                                              op_lane(op, j % 16, i % KB), kgroup_of(op));
+              if (op == OP_F64)
+                reinterpret_cast<double*>(tabS.data())[e] = v;
+              else
+                reinterpret_cast<float*>(tabS.data())[e] = (float)v;
+            }
           }
           // analysis: rows = degrees i, k = rings j; FP32 / FP64 in k-groups
           {
