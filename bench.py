@@ -474,8 +474,10 @@ def main():
     # nodes 1-4
     measured = {("sweep_node", "fp32", 255, 16, None): 280.71e6,
                 ("ring", "fp32", 255, 16, 0): 114.56e6,
-                ("leg_anal", "fp32", 255, 16, 0): 160.33e6,
-                ("leg_anal", "fp32", 255, 16, 6): 117.82e6}
+                ("leg_synth", "fp32", 255, 16, 0): 108.03e6,
+                ("leg_synth", "fp32", 255, 16, 3): 101.47e6,
+                ("leg_anal", "fp32", 255, 16, 0): 115.59e6,
+                ("leg_anal", "fp32", 255, 16, 6): 117.41e6}
     stage_of = {"leg_synth": "synth", "leg_anal": "anal", "ring": "ring"}
     if dom is not None:
         var = rmx["tuned"].get("fine", {}).get(B, {}).get(stage_of.get(dom)) if dom in stage_of else None
