@@ -339,7 +339,7 @@ __device__ __forceinline__ void mma_loop_grp(const void* __restrict__ A,
 // groups then rem k-blocks of a padded last group.  Rows r >= nr and columns
 // c >= nc repeat the last valid one (their results are not stored), so the
 // loop has no branches; each valid block sees the k-blocks in the order and
-// FP32 chains of mma_tile: the same bits.
+// FP32 chains of mma_loop_rc: the same bits.
 template <class Op, int PF, int RT, int CT>
 __device__ __forceinline__ void mma_tile_grp(const void* __restrict__ A, const void* __restrict__ B,
                                              long long ta, long long astep, long long tb,
@@ -507,127 +507,6 @@ __device__ __forceinline__ void mma_loop(const void* __restrict__ A, const void*
     mma_loop_rc<Op, PF, false, true>(A, B, ta, astep, tb, bstep, nk, lane, acc00, acc01, acc10, acc11);
   else
     mma_loop_rc<Op, PF, false, false>(A, B, ta, astep, tb, bstep, nk, lane, acc00, acc01, acc10, acc11);
-}
-
-// K loop of one wave's RT x CT blocks (rows ta + r, columns tb + c; r < nr,
-// c < nc valid): RT + CT operand loads feed RT CT MFMAs per k-block, so larger
-// tiles re-read the operands fewer times.  Every block accumulates its k-blocks
-// in the same order as mma_loop, so the results are the same bits.
-// Full RT x CT tile: the branch-free form of mma_loop_rc (clamped prefetch,
-// scalar addresses, tail after the loop).
-template <class Op, int PF, int RT, int CT>
-__device__ __forceinline__ void mma_tile_full(const void* __restrict__ A, const void* __restrict__ B,
-                                              long long ta, long long astep, long long tb,
-                                              long long bstep, int nk, int lane,
-                                              typename Op::C (&acc)[RT][CT]) {
-  ta = wave_uniform(ta);
-  tb = wave_uniform(tb);
-  astep = wave_uniform(astep);
-  bstep = wave_uniform(bstep);
-  nk = __builtin_amdgcn_readfirstlane(nk);
-  if (nk <= 0) return;
-  constexpr bool SPL = SplitAcc<Op>::value;
-  static_assert(!SPL || PF % 2 == 0, "two accumulation chains need an even prefetch depth");
-  typename Op::C x[RT][CT] = {};   // odd k-blocks (SPL)
-  typename Op::A a[PF][RT], b[PF][CT];
-#pragma unroll
-  for (int s = 0; s < PF; ++s) {
-    const long long k = s < nk ? s : nk - 1;
-#pragma unroll
-    for (int r = 0; r < RT; ++r) a[s][r] = Op::load(A, ta + k * astep + r, lane);
-#pragma unroll
-    for (int c = 0; c < CT; ++c) b[s][c] = Op::load(B, tb + k * bstep + c, lane);
-  }
-  int k0 = 0;
-  for (; k0 + PF <= nk; k0 += PF) {
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          typename Op::C& t = (SPL && (s & 1)) ? x[r][c] : acc[r][c];
-          t = Op::mma(a[s][r], b[s][c], t);
-        }
-      const int kn = k0 + s + PF;
-      const long long k = kn < nk ? kn : nk - 1;
-#pragma unroll
-      for (int r = 0; r < RT; ++r) a[s][r] = Op::load(A, ta + k * astep + r, lane);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[s][c] = Op::load(B, tb + k * bstep + c, lane);
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < PF - 1; ++s) {
-    if (k0 + s < nk) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          typename Op::C& t = (SPL && (s & 1)) ? x[r][c] : acc[r][c];
-          t = Op::mma(a[s][r], b[s][c], t);
-        }
-    }
-  }
-  if constexpr (SPL) {
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[r][c] += x[r][c];
-  }
-}
-
-template <class Op, int PF, int RT, int CT>
-__device__ __forceinline__ void mma_tile(const void* __restrict__ A, const void* __restrict__ B,
-                                         long long ta, long long astep, long long tb,
-                                         long long bstep, int nk, int nr, int nc, int lane,
-                                         typename Op::C (&acc)[RT][CT]) {
-  if (__builtin_amdgcn_readfirstlane(nr) == RT && __builtin_amdgcn_readfirstlane(nc) == CT) {
-    mma_tile_full<Op, PF, RT, CT>(A, B, ta, astep, tb, bstep, nk, lane, acc);
-    return;
-  }
-  constexpr bool SPL = SplitAcc<Op>::value;
-  typename Op::C x[RT][CT] = {};   // odd k-blocks (SPL)
-  typename Op::A a[PF][RT], b[PF][CT];
-#pragma unroll
-  for (int s = 0; s < PF; ++s) {
-    const bool ok = s < nk;
-#pragma unroll
-    for (int r = 0; r < RT; ++r) a[s][r] = (ok && r < nr) ? Op::load(A, ta + s * astep + r, lane) : Op::zero();
-#pragma unroll
-    for (int c = 0; c < CT; ++c) b[s][c] = (ok && c < nc) ? Op::load(B, tb + s * bstep + c, lane) : Op::zero();
-  }
-  for (int k0 = 0; k0 < nk; k0 += PF) {
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      const int kb = k0 + s;
-      if (kb < nk) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-#pragma unroll
-          for (int c = 0; c < CT; ++c)
-            if (r < nr && c < nc) {
-              typename Op::C& t = (SPL && (s & 1)) ? x[r][c] : acc[r][c];
-              t = Op::mma(a[s][r], b[s][c], t);
-            }
-        const int kn = kb + PF;
-        if (kn < nk) {
-#pragma unroll
-          for (int r = 0; r < RT; ++r)
-            if (r < nr) a[s][r] = Op::load(A, ta + kn * astep + r, lane);
-#pragma unroll
-          for (int c = 0; c < CT; ++c)
-            if (c < nc) b[s][c] = Op::load(B, tb + kn * bstep + c, lane);
-        }
-      }
-    }
-  }
-  if constexpr (SPL) {
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[r][c] += x[r][c];
-  }
 }
 
 }  // namespace pfsh
