@@ -163,3 +163,163 @@ def test_converged_result_independent_of_qi(lv):
     b, _, _ = _converge(lv, be, 120.0, th0, 60)
     for v in range(3):
         assert np.abs(a[-1][v] - b[-1][v]).max() <= 1e-12 * np.abs(a[-1][v]).max()
+
+
+# ---------------------------------------------------------------------------
+# Pins of the correction terms of one sweep (Sec. 5.1.1, eq.
+# update_equation_sdcq_discrete_form).  The collocation pins above only see
+# the fixed point, where every correction term vanishes; the three pins below
+# constrain the terms themselves: the order gained per sweep (stated in
+# Sec. 5.1.1), the explicit correction reducing to forward Euler over the
+# node substeps, and the stiff-limit collapse that the LU choice of qI gives.
+# The mutant tests plant plausible mistakes in copies of the oracle's
+# matrices and show which pin catches each.
+
+
+def _order_errors(sd, dts, kmax, lvn, A, th0):
+    """One-step error after k = 1..kmax sweeps from the spread guess, against
+    exp(dt A) of the probed linear-Coriolis operator; per variable, max."""
+    K = lvn.K
+    x0 = np.concatenate([th0.reshape(-1).real, th0.reshape(-1).imag])
+    errs = np.zeros((kmax + 1, len(dts)))
+    for i, dt in enumerate(dts):
+        r = expm(dt * A) @ x0
+        ref = (r[: 3 * K] + 1j * r[3 * K:]).reshape(3, K)
+        th, fe, fi = sdc.spread(lvn, th0, sd.M + 1, True)
+        for k in range(1, kmax + 1):
+            th, fe, fi = sdc.sweep(lvn, sd, dt, th, fe, fi, None, True)
+            errs[k, i] = max(np.abs(th[-1][v] - ref[v]).max() / np.abs(ref[v]).max() for v in range(3))
+    return errs
+
+
+def test_each_sweep_raises_the_order_by_one():
+    """Sec. 5.1.1: each sweep raises the formal order by one until the order
+    of the quadrature is reached.  From the spread guess (order 0), k sweeps
+    give a one-step error O(dt^(k+1)); the slope of log(error) over log(dt)
+    is fitted for k = 1..2M (3 nodes) and k = 1..6 (5 nodes; the collocation
+    order 2M = 8 itself is checked by test_collocation_order_vs_expm)."""
+    Tn = 6
+    lvn = swe.Level(Tn, 12, 24)
+    A = _probe_matrix(lvn)
+    th0 = inputs.random_spectrum(Tn, 3)
+    for nn, dts, kmax in ((3, (300.0, 600.0, 1200.0), 4), (5, (1000.0, 2000.0, 4000.0), 6)):
+        errs = _order_errors(sdc.SDC(nn), dts, kmax, lvn, A, th0)
+        slopes = [np.polyfit(np.log(dts), np.log(errs[k]), 1)[0] for k in range(1, kmax + 1)]
+        for k, s in enumerate(slopes, start=1):
+            assert abs(s - (k + 1)) < 0.45, (nn, k, slopes)
+
+
+def _zero_history_sweep(sd, lvn, st, dt):
+    """A sweep whose previous iterate has F = 0 at every node (inputs the
+    sweep accepts as data): only the correction terms act."""
+    nn = sd.M + 1
+    th = np.repeat(st[None], nn, axis=0)
+    z = np.zeros_like(th)
+    return sdc.sweep(lvn, sd, dt, th, z, z.copy(), None, True)
+
+
+def _euler_over_nodes(sd, lvn, st, dt):
+    """Forward Euler from node 1 over the substeps dt (tau_{m+1} - tau_m)."""
+    out = [st, st]
+    for m in range(1, sd.M):
+        h = dt * (sd.nodes[m + 1] - sd.nodes[m])
+        out.append(out[-1] + h * swe.explicit_rhs(lvn, out[-1], True))
+    return np.array(out)
+
+
+@pytest.fixture(scope="module")
+def lv_explicit_only():
+    """Phibar = nu = 0 and a state with Phi = 0: F_I = 0 along the sweep,
+    F_E = the linear Coriolis terms (test flag)."""
+    return swe.Level(6, 12, 24, swe.Physics(phibar=0.0, nu=0.0))
+
+
+@pytest.mark.parametrize("nn", [3, 5])
+def test_explicit_correction_is_forward_euler_over_nodes(lv_explicit_only, nn):
+    """qE is forward Euler (Sec. 5.1.1): with the previous iterate's F set to
+    zero and F_I = 0, the Q-form update Theta^{m+1} = Theta^0 + dt sum_{j=1}^m
+    qE_{m+1,j} F_E(Theta^j) is Euler stepping over the node substeps starting
+    from Theta^1 = Theta^0 (the explicit sum starts at j = 1)."""
+    sd = sdc.SDC(nn)
+    st = inputs.random_spectrum(6, 5)
+    st[0] = 0.0
+    out, fe, fi = _zero_history_sweep(sd, lv_explicit_only, st, 500.0)
+    assert np.abs(fi).max() == 0.0
+    ref = _euler_over_nodes(sd, lv_explicit_only, st, 500.0)
+    for i in range(nn):
+        for v in (1, 2):
+            assert np.abs(out[i, v] - ref[i, v]).max() <= 1e-15 * np.abs(ref[i, v]).max(), (i, v)
+
+
+def _stiff_error(sd, nu, nsweeps):
+    """Max over nodes 1..M and variables of the distance to the collocation
+    solution after `nsweeps` sweeps from the spread guess, for F_E = 0
+    (Omega = 0, linear-Coriolis flag) and a diffusion-dominated F_I."""
+    Tn = 10
+    lvs = swe.Level(Tn, 16, 32, swe.Physics(omega=0.0, nu=nu))
+    th0 = inputs.random_spectrum(Tn, 8) + inputs.mean_geopotential(Tn)
+    dt = 100.0
+    th, fe, fi = sdc.spread(lvs, th0, sd.M + 1, True)
+    hist = []
+    for _ in range(max(nsweeps, 60)):
+        th, fe, fi = sdc.sweep(lvs, sd, dt, th, fe, fi, None, True)
+        hist.append(th.copy())
+    ref, got = hist[-1], hist[nsweeps - 1]
+    return max(np.abs(got[1:, v] - ref[1:, v]).max() / np.abs(ref[:, v]).max() for v in range(3))
+
+
+@pytest.mark.parametrize("nn", [3, 5])
+def test_lu_qi_collapses_in_the_stiff_limit(nn):
+    """qI = U^T of the LU factorization of Q^T (Sec. 5.1.1, the choice cited
+    for stiff problems): in the stiff limit the error propagation of a sweep
+    tends to I - L^T, which is nilpotent, so after M sweeps the iterate
+    reaches the collocation solution up to a term that vanishes as the
+    stiffness grows (here dt nu n(n+1)/a^2 >= 5e3 for every n >= 1)."""
+    sd = sdc.SDC(nn)
+    e1 = _stiff_error(sd, 1e15, sd.M)
+    e2 = _stiff_error(sd, 1e16, sd.M)
+    assert e1 < 2e-4 and e2 < 0.2 * e1, (e1, e2)
+
+
+def _implicit_euler_qi(sd):
+    QI = np.zeros_like(sd.QI)
+    for i in range(1, sd.M + 1):
+        for j in range(1, i + 1):
+            QI[i, j] = sd.nodes[j] - sd.nodes[j - 1]
+    return QI
+
+
+@pytest.mark.parametrize("nn", [3, 5])
+def test_planted_sweep_mistakes_are_caught(lv_explicit_only, nn):
+    """Mutants of the correction terms (planted in copies of the oracle's
+    matrices) keep the collocation fixed point and the order gained per
+    sweep, but fail the Euler or the stiff-limit pin."""
+    st = inputs.random_spectrum(6, 5)
+    st[0] = 0.0
+    ref = _euler_over_nodes(sdc.SDC(nn), lv_explicit_only, st, 500.0)
+
+    def euler_ok(sd):
+        out, _, _ = _zero_history_sweep(sd, lv_explicit_only, st, 500.0)
+        return all(np.abs(out[i, v] - ref[i, v]).max() <= 1e-12 * np.abs(ref[i, v]).max()
+                   for i in range(nn) for v in (1, 2))
+
+    assert euler_ok(sdc.SDC(nn))
+    # qE row m used for node m+1
+    mut = sdc.SDC(nn)
+    QE = np.zeros_like(mut.QE)
+    QE[1:] = mut.QE[:-1]
+    mut.QE = QE
+    assert not euler_ok(mut)
+    # explicit sum over j < m instead of j <= m
+    mut = sdc.SDC(nn)
+    mut.QE = np.tril(mut.QE, -2)
+    assert not euler_ok(mut)
+    # qI: implicit Euler weights, or the LU rows shifted below the diagonal
+    mut = sdc.SDC(nn)
+    mut.QI = _implicit_euler_qi(mut)
+    assert _stiff_error(mut, 1e15, mut.M) > 1e-2
+    mut = sdc.SDC(nn)
+    shifted = np.diag(np.diag(mut.QI))
+    shifted[2:, 1:] += np.tril(mut.QI[1:-1, 1:], -1)
+    mut.QI = shifted
+    assert _stiff_error(mut, 1e15, mut.M) > 1e-2

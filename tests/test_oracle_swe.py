@@ -155,3 +155,53 @@ def test_nonlinear_terms_vs_finite_differences():
         got = [evaluate(fe[i], Tn, np.array(lam), np.array(phi)) for i in range(3)]
         for g_, ref, scale in zip(got, (nphi, nzeta, ndelta), np.abs(fe).max(axis=1)):
             assert abs(g_ - ref) < 2e-6 * scale * 10, (lam, phi, g_, ref)
+
+
+def _mode_block(lv, k):
+    """The 3 x 3 complex matrix of F_I = L at spectral slot k, probed with unit
+    vectors through implicit_rhs (L acts on each mode separately)."""
+    out = np.zeros((3, 3), dtype=np.complex128)
+    for v in range(3):
+        e = np.zeros((3, lv.K), dtype=np.complex128)
+        e[v, k] = 1.0
+        out[:, v] = swe.implicit_rhs(lv, e)[:, k]
+    return out
+
+
+@pytest.mark.parametrize("nu", [0.0, 1e5])
+def test_linear_part_has_gravity_wave_frequencies(nu):
+    """Sec. 2, eq. linear_wave_motion_induced_by_gravitational_forces: the
+    linear part carries gravity waves, Phi'' = -Phibar n(n+1)/a^2 Phi at
+    nu = 0, so the (Phi, delta) block of each mode has eigenvalues
+    +-i omega_n with omega_n = sqrt(n(n+1) Phibar)/a, and zeta is stationary;
+    diffusion shifts all three by nu lam_n = -nu n(n+1)/a^2."""
+    lvn = swe.Level(T, NLAT, NLON, swe.Physics(nu=nu, omega=0.0))
+    a, pb = lvn.phys.radius, lvn.phys.phibar
+    for k in range(0, lvn.K, 5):
+        n = lvn.g.n_of[k]
+        w = math.sqrt(n * (n + 1) * pb) / a
+        d = -nu * n * (n + 1) / a ** 2
+        ev = np.linalg.eigvals(_mode_block(lvn, k))
+        ev = ev[np.argsort(ev.imag)]
+        ref = np.array([d - 1j * w, d + 0j, d + 1j * w])
+        assert np.abs(ev - ref).max() <= 1e-12 * max(w, abs(d), 1e-30), (k, ev, ref)
+
+
+def test_implicit_solve_matches_eigen_decomposition(lv):
+    """(I - beta L)^{-1} b through the eigen-decomposition of each probed mode
+    block: eigenvalues 1/(1 - beta mu) for mu in {nu lam_n, nu lam_n +- i omega_n}
+    (the closed forms above), eigenvectors from numpy."""
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((3, lv.K)) + 1j * rng.standard_normal((3, lv.K))
+    beta = 123.0
+    x = swe.implicit_solve(lv, beta, b)
+    a, pb, nu = lv.phys.radius, lv.phys.phibar, lv.phys.nu
+    for k in range(1, lv.K, 11):
+        n = lv.g.n_of[k]
+        _, V = np.linalg.eig(_mode_block(lv, k))
+        mus = np.linalg.solve(V, _mode_block(lv, k) @ V).diagonal()
+        w = math.sqrt(n * (n + 1) * pb) / a
+        d = -nu * n * (n + 1) / a ** 2
+        closed = np.array([min((d - 1j * w, d, d + 1j * w), key=lambda z: abs(z - mu)) for mu in mus])
+        ref = V @ ((np.linalg.solve(V, b[:, k])) / (1.0 - beta * closed))
+        np.testing.assert_allclose(x[:, k], ref, rtol=1e-11, atol=1e-13 * np.abs(b[:, k]).max())
