@@ -146,6 +146,24 @@ pfsh_status pfsh_sdc_sweep(pfsh_level* level, double dt, void* theta, void* f_ex
 pfsh_status pfsh_residual(pfsh_level* level, double dt, const void* theta, const void* f_expl,
                           const void* f_impl, const void* tau, double* out, int batch, void* stream);
 
+/* Allocation-free variant of pfsh_residual, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same kernels and the same result, with the
+ * per-block partial maxima in a static device array of
+ * PFSH_RESIDUAL_SCRATCH_DOUBLES doubles (4 MiB) that the library holds on
+ * every GPU it runs on until the process ends, instead of the level's
+ * workspace.  Nothing is allocated or freed by the call.  The partials need
+ * batch * 3 * ceil(K / 256) doubles; a larger request returns PFSH_ESHAPE
+ * before anything is enqueued (batch may exceed the level's max_batch, the
+ * call does not use the level's workspace; batch <= 65535).  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (two streams, two
+ * threads) race and must be ordered by the caller.  Arguments and output as
+ * pfsh_residual. */
+#define PFSH_RESIDUAL_SCRATCH_DOUBLES (1 << 19)
+pfsh_status pfsh_residual_noalloc(pfsh_level* level, double dt, const void* theta,
+                                  const void* f_expl, const void* f_impl, const void* tau,
+                                  double* out, int batch, void* stream);
+
 /* Synchronous check of a [count] float64 device array: PFSH_ENONFINITE if any
  * entry is NaN/Inf, PFSH_OK otherwise (waits for `stream`). */
 pfsh_status pfsh_check_finite(const double* values, int count, void* stream);

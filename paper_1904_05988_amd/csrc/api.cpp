@@ -178,6 +178,22 @@ extern "C" pfsh_status pfsh_residual(pfsh_level* lv, double dt, const void* thet
                                (hipStream_t)stream));
 }
 
+extern "C" pfsh_status pfsh_residual_noalloc(pfsh_level* lv, double dt, const void* theta,
+                                             const void* f_expl, const void* f_impl,
+                                             const void* tau, double* out, int batch,
+                                             void* stream) {
+  if (!lv || !theta || !f_expl || !f_impl || !out) return PFSH_EINVAL;
+  if (!(dt > 0) || !std::isfinite(dt)) return PFSH_EINVAL;
+  if (batch < 1 || batch > 65535) return PFSH_ESHAPE;
+  if (residual_part_len(lv, batch) > kResidualScratchDoubles) return PFSH_ESHAPE;
+  double* part = residual_scratch(lv->device);   // looked up when the level was created
+  if (!part) return PFSH_EHIP;
+  DeviceGuard g(lv->device);
+  return st_of(launch_residual_into(lv, dt, (const double*)theta, (const double*)f_expl,
+                                    (const double*)f_impl, (const double*)tau, out, part, batch,
+                                    (hipStream_t)stream));
+}
+
 extern "C" pfsh_status pfsh_check_finite(const double* values, int count, void* stream) {
   if (!values || count < 0) return PFSH_EINVAL;
   if (count == 0) return PFSH_OK;

@@ -2,6 +2,8 @@
 // and implicit solve, the SDC sweep accumulation, the collocation residual and
 // the space-time transfers.  All are bandwidth-bound element-wise passes over
 // [batch][...][3][K] complex128 arrays.
+#include <mutex>
+
 #include "mfma_ops.h"
 
 namespace pfsh {
@@ -1133,21 +1135,67 @@ hipError_t launch_sweep_step(const pfsh_level* lv, int node, int asm_node, doubl
   }
 }
 
-hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
-                           const double* fi, const double* tau, double* out, int batch,
-                           hipStream_t s) {
+long long residual_part_len(const pfsh_level* lv, int batch) {
+  return (long long)batch * 3 * ((lv->K + 255) / 256);
+}
+
+// The residual's partial maxima go to `part` (residual_part_len doubles).
+hipError_t launch_residual_into(const pfsh_level* lv, double dt, const double* theta,
+                                const double* fe, const double* fi, const double* tau, double* out,
+                                double* part, int batch, hipStream_t s) {
   const int nblk = (lv->K + 255) / 256;
   const SdcMat sm = sdc_of(lv);
 #define PFSH_RES(NN)                                                                          \
   hipLaunchKernelGGL(k_residual_part<NN>, dim3(nblk, 3, batch), dim3(256), 0, s, theta, fe, fi, \
-                     tau, lv->red, lv->K, dt, sm)
+                     tau, part, lv->K, dt, sm)
   PFSH_NN_SWITCH(lv->nn, PFSH_RES)
 #undef PFSH_RES
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residual_final, dim3((batch * 3 + 127) / 128), dim3(128), 0, s, lv->red,
+  hipLaunchKernelGGL(k_residual_final, dim3((batch * 3 + 127) / 128), dim3(128), 0, s, part,
                      out, nblk, batch * 3);
   return hipGetLastError();
+}
+
+hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
+                           const double* fi, const double* tau, double* out, int batch,
+                           hipStream_t s) {
+  return launch_residual_into(lv, dt, theta, fe, fi, tau, out, lv->red, batch, s);
+}
+
+// ----------------------------------------- residual scratch without allocation
+// The partial maxima of pfsh_residual_noalloc live in this file-scope device
+// array instead of a level's workspace: every GPU the library runs on holds
+// its own copy until the process ends.  In host code the name `scratch` only
+// stands for the symbol; the device address of each GPU's copy comes from
+// hipGetSymbolAddress (residual_scratch_setup, called once per device with
+// that device current) and only that address is handed to kernels.  Every
+// call on one GPU shares the array; the partial-maxima kernel writes every
+// entry it later reads, so nothing has to start at zero.
+__attribute__((used)) static __device__ __align__(256) double scratch[kResidualScratchDoubles];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t residual_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+double* residual_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_spread(const pfsh_level* lv, double* a, int batch, hipStream_t s) {

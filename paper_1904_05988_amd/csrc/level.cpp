@@ -76,6 +76,12 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   int prev = 0;
   (void)hipGetDevice(&prev);
   if (hipSetDevice(device) != hipSuccess) return PFSH_EHIP;
+  // this device's copy of the static residual scratch (pfsh_residual_noalloc)
+  if (residual_scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipSetDevice(prev);
+    return PFSH_EHIP;
+  }
 
   pfsh_level* lv = new (std::nothrow) pfsh_level();
   if (!lv) return PFSH_ENOMEM;

@@ -223,6 +223,19 @@ hipError_t launch_node_fused(const pfsh_level* lv, int node, int asm_node, doubl
 hipError_t launch_residual(const pfsh_level* lv, double dt, const double* theta, const double* fe,
                            const double* fi, const double* tau, double* out, int batch,
                            hipStream_t s);
+// The same with the partial maxima in `part` (residual_part_len(lv, batch)
+// doubles) instead of the level's workspace.
+long long residual_part_len(const pfsh_level* lv, int batch);
+hipError_t launch_residual_into(const pfsh_level* lv, double dt, const double* theta,
+                                const double* fe, const double* fi, const double* tau, double* out,
+                                double* part, int batch, hipStream_t s);
+// Allocation-free residual scratch: a static device array of
+// kResidualScratchDoubles doubles per GPU.  residual_scratch_setup looks up the
+// current device's copy (call with `device` current; once per device, later
+// calls return at once); residual_scratch returns it (nullptr before setup).
+constexpr long long kResidualScratchDoubles = PFSH_RESIDUAL_SCRATCH_DOUBLES;
+hipError_t residual_scratch_setup(int device);
+double* residual_scratch(int device);
 hipError_t launch_spread(const pfsh_level* lv, double* a, int batch, hipStream_t s);
 hipError_t launch_restrict(const pfsh_level* f, const pfsh_level* c, const double* in_f,
                            double* out_c, int batch, hipStream_t s);

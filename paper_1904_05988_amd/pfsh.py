@@ -48,6 +48,7 @@ _SIGS = {
     "pfsh_implicit_solve": ([_P, _D, _P, _P, _I, _P], _I),
     "pfsh_sdc_sweep": ([_P, _D, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_residual": ([_P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
+    "pfsh_residual_noalloc": ([_P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_check_finite": ([_P, _I, _P], _I),
     "pfsh_spread": ([_P, _P, _P, _P, _I, _P], _I),
     "pfsh_restrict": ([_P, _P, _P, _P, _I, _P], _I),
@@ -297,6 +298,24 @@ class Level:
         _need(out, F64, (B, 3), "out")
         _check(lib().pfsh_residual(self._h, float(dt), _ptr(theta), _ptr(f_expl), _ptr(f_impl),
                                    _ptr(tau), _ptr(out), B, _stream(theta)), "pfsh_residual")
+        return out
+
+    def residual_noalloc(self, dt, theta, f_expl, f_impl, tau=None, out=None):
+        """pfsh_residual_noalloc: the residual with its partial maxima in the
+        library's static device scratch (no allocation; `out` must be given
+        by callers that cannot allocate)."""
+        B = theta.shape[0]
+        shape = (B, self.n_nodes, 3, self.K)
+        for t, n in ((theta, "theta"), (f_expl, "f_expl"), (f_impl, "f_impl")):
+            _need(t, C128, shape, n)
+        if tau is not None:
+            _need(tau, C128, shape, "tau")
+        if out is None:
+            out = torch.empty((B, 3), dtype=F64, device=theta.device)
+        _need(out, F64, (B, 3), "out")
+        _check(lib().pfsh_residual_noalloc(self._h, float(dt), _ptr(theta), _ptr(f_expl),
+                                           _ptr(f_impl), _ptr(tau), _ptr(out), B, _stream(theta)),
+               "pfsh_residual_noalloc")
         return out
 
     def spread(self, theta=None, f_expl=None, f_impl=None):
