@@ -1,0 +1,104 @@
+"""The benchmarked PFASST block at full size against the oracle.
+
+Two-level PFASST(16, 5, 3, 8) of Sec. 5.2 (Algorithm 1): fine T255 on 384 x
+768, coarse T127 on 192 x 384, dt = 60 s, 16 time steps as one batch, seed 3.
+tests/golden/pfasst_t255_t127_16x8.npz holds the oracle's values on a fixed
+sample of spectral slots (every 137th slot and the zonal modes m = 0, n <= 15),
+written by tests/golden/make_pfasst_t255.py from the oracle alone.  Compared
+element by element on those slots, each time step normalized by its own
+reference values (the paper's max-norm per variable):
+  * the FP64 block after the predictor, after every iteration (fine last node,
+    and node 0 after step D of iterations 1, 4, 7) and at the end: <= 1e-11;
+  * the benchmark's mixed recipe (FP32 transforms, the last two iterations on
+    FP64 fine levels, FP64 coarse level) at the end: <= 1e-6."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1904_05988_amd import inputs, pfsh
+from tests._gpu import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "pfasst_t255_t127_16x8.npz")
+
+
+def _err(got, ref):
+    """Max over time steps of the per-step normalized error per variable, on
+    the sampled slots; the geopotential's mean slot (0,0) is left out of the
+    denominator (it is sqrt(2) Phibar)."""
+    out = np.zeros(3)
+    for n in range(ref.shape[0]):
+        for v in range(3):
+            den = np.abs(ref[n, v]).copy()
+            if v == 0:
+                den[0] = 0.0          # slot (0,0) is the first sampled slot
+            e = np.abs(got[n, v] - ref[n, v]).max() / den.max()
+            out[v] = max(out[v], e)
+    return out
+
+
+@pytest.fixture(scope="module")
+def golden():
+    d = np.load(GOLDEN)
+    meta = d["meta"]
+    assert tuple(int(x) for x in meta[:8]) == (255, 384, 768, 5, 127, 192, 384, 3)
+    assert int(meta[8]) == 16 and int(meta[9]) == 8 and meta[10] == 60.0 and int(meta[11]) == 3
+    assert d["slots"][0] == 0
+    return {k: d[k] for k in d.files}
+
+
+def _run(golden, fine_first, fine_last, n64):
+    """The block as the benchmark runs it (iteration order, graphs off); the
+    fine level switches to `fine_last` for the final n64 iterations.  Returns
+    the sampled values at the points the golden file stores."""
+    gc = pfsh.Level(127, 192, 384, 3, max_batch=16)
+    s = golden["slots"]
+    th0 = to_dev(inputs.seeded_state(255, 3)[None])
+    pf = pfsh.Pfasst(fine_first, gc, 16)
+    thf, fef, fif = (fine_first.space_time(16) for _ in range(3))
+    pf.predict(60.0, th0, thf, fef, fif)
+    out = {"pred": to_host(thf[:, -1])[..., s], "last": [], "first": []}
+    for k in range(8):
+        if k == 8 - n64:
+            pf.set_levels(fine_last, gc)
+        pf.iterate(60.0, thf, fef, fif, last=(k == 7))
+        if k < 7:
+            out["last"].append(to_host(thf[:, -1])[..., s])
+            if k in (0, 3, 6):
+                out["first"].append(to_host(thf[:, 0])[..., s])
+    out["final"] = to_host(thf[:, -1])[..., s]
+    pf.close()
+    return out
+
+
+def test_fp64_block_matches_oracle(golden):
+    gf = pfsh.Level(255, 384, 768, 5, max_batch=16)
+    got = _run(golden, gf, gf, 0)
+    errs = {"pred": _err(got["pred"], golden["pred"])}
+    for k in range(7):
+        errs[f"last{k + 1}"] = _err(got["last"][k], golden["last"][k])
+    for i, k in enumerate((1, 4, 7)):
+        errs[f"first{k}"] = _err(got["first"][i], golden["first"][i])
+    errs["final"] = _err(got["final"], golden["final"])
+    print({k: [f"{x:.2e}" for x in v] for k, v in errs.items()})
+    for k, e in errs.items():
+        assert np.all(e <= 1e-11), (k, e)
+
+
+def test_mixed_recipe_matches_oracle(golden):
+    gf32 = pfsh.Level(255, 384, 768, 5, max_batch=16, precision="fp32")
+    gf64 = pfsh.Level(255, 384, 768, 5, max_batch=16)
+    got = _run(golden, gf32, gf64, 2)
+    per_iter = [_err(got["last"][k], golden["last"][k]) for k in range(7)]
+    final = _err(got["final"], golden["final"])
+    print("mixed per iteration", [[f"{x:.2e}" for x in e] for e in per_iter], "final", final)
+    assert np.all(final <= 1e-6), final
+    # the FP32 iterations themselves stay within the transform round-off
+    for k, e in enumerate(per_iter):
+        assert np.all(e <= 5e-6), (k, e)
+    torch.cuda.synchronize()

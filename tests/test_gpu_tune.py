@@ -21,8 +21,12 @@ def _rhs(gl, x):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 3), (63, 96, 192, 13), (127, 192, 384, 16)])
+@pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 3), (63, 96, 192, 13), (127, 192, 384, 16),
+                                           (255, 384, 768, 16)])
 def test_legendre_variants_are_bitwise_equal(prec, T, nlat, nlon, B):
+    """Every synthesis and analysis variant, up to the fine level of the PFASST
+    workload (T255, 16 slices), where the tuner keeps the 64 x 64 synthesis
+    tiles and the tall analysis tiles."""
     gl = pfsh.Level(T, nlat, nlon, 3, max_batch=B, precision=prec)
     x = to_dev(seeded(T, range(B)))
     base = _rhs(gl, x)
