@@ -11,14 +11,17 @@ iteration stops after its fine sweep), then the fine collocation residual.
 "sweeps/s" counts batched fine sweeps (all 16 slices) per second.
 
 The headline block runs the transform stages in mixed precision (FP32 by
-default) and its last four iterations with FP64 fine levels; the same block in
+default) and its last two iterations with FP64 fine levels; the same block in
 plain FP64 is timed next to it, and the states of the two are compared after
 every iteration (and against serial FP64 SDC on the same time steps, the
 collocation solution PFASST converges to).
-Iterations are replayed from captured HIP graphs.  The dominant kernel's
-roofline fraction is measured with HIP events around its launches in a second
-pass over the same blocks with direct launches; the oracle is timed on the
-host cores on a bounded sample.
+Iterations are replayed from captured HIP graphs.  Every kernel of every level
+is timed with HIP events around its launches in a second pass over the same
+blocks with direct launches; the roofline line names the kernel with the
+largest time per block, against the bound (MFMA or HBM) its algorithmic work
+per launch sets.  The standalone batched SH round trip (synthesis + analysis)
+is timed as well.  The oracle is timed on the host cores on a bounded sample,
+with all threads and with one.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU (time slices are the batch axis).
@@ -136,6 +139,146 @@ def sweep_node_bytes(T, nn, B, rsz):
     return tot / M
 
 
+def table_bytes(T, nlat, prec):
+    """Bytes of one packed Legendre table (degrees to T+1, northern rings):
+    FP64 8 B per value, FP32 4 B, BF16x3 a hi and a lo bf16 (4 B)."""
+    deg = sum(npar(T, m, p) for m in range(T + 1) for p in (0, 1))
+    return deg * (nlat // 2) * (8 if prec == "fp64" else 4)
+
+
+def kernel_work(kernel, T, nlat, nlon, nn, b, prec):
+    """Algorithmic work of one launch of a profiled kernel at batch b: useful
+    MFMA flops and the bytes it must move through HBM (tables, operands in
+    and out, FP64 spectral states), None for kernels without a model.  The
+    sweep node of a batch of one or two slices on FP64 / FP32 levels is the
+    fused per-order kernel (k_node_fused): the analysis of the previous
+    node's products, the node update and the synthesis of the new state."""
+    rsz = 8 if prec == "fp64" else 4
+    L, J = T + 1, nlat // 2
+    K = (T + 1) * (T + 2) // 2
+    deg = sum(npar(T, m, p) for m in range(T + 1) for p in (0, 1))
+    st = 3 * K * 16 * b
+    op = {"fp64": "OpF64", "fp32": "OpF32", "bf16x3": "OpBF3"}[prec]
+    xs = deg * 8 * b * (4 if prec == "bf16x3" else rsz)           # synthesis operand
+    f4 = 4 * 2 * L * J * b * 2 * rsz                                # Fourier coefficients
+    g = 5 * 2 * L * J * b * 2 * (8 if prec == "fp64" else 4)        # analysis operand
+    y = 5 * (K + T + 1) * b * 2 * rsz                               # analysed products
+    if kernel == "leg_synth":
+        return {"flops": legendre_flops(T, nlat, 8 * b), "bytes": table_bytes(T, nlat, prec) + xs + f4,
+                "symbol": f"k_leg_synth*<{op}>"}
+    if kernel == "leg_anal":
+        return {"flops": legendre_flops(T, nlat, 10 * b), "bytes": table_bytes(T, nlat, prec) + g + y,
+                "symbol": f"k_leg_anal*<{op}>"}
+    if kernel == "ring":
+        return {"flops": 0.0, "bytes": ring_bytes(T, nlat, rsz, b), "symbol": f"k_ring_rhs<{op}, {nlon}>"}
+    if kernel == "prep":
+        return {"flops": 0.0, "bytes": 2 * st + xs, "symbol": f"k_prep_rhs<{op}>"}
+    if kernel == "assemble":
+        return {"flops": 0.0, "bytes": y + st, "symbol": "k_assemble"}
+    if kernel == "sweep_node":
+        if b <= 2 and prec in ("fp64", "fp32"):
+            states = sweep_node_bytes(T, nn, b, rsz) - (y + xs)
+            return {"flops": legendre_flops(T, nlat, 8 * b) + legendre_flops(T, nlat, 10 * b),
+                    "bytes": 2 * table_bytes(T, nlat, prec) + g + f4 + states,
+                    "symbol": f"k_node_fused<{op}, {nn}>"}
+        return {"flops": 0.0, "bytes": sweep_node_bytes(T, nn, b, rsz), "symbol": f"k_sweep_step<{op}, {nn}>"}
+    return None
+
+
+def roofline_of(w, avg_s, prec):
+    """Roofline of one kernel from its work per launch and average launch
+    time: the bound is the resource whose peak needs the longer time for that
+    work (MFMA flops at the precision's dense peak, or bytes at 8 TB/s)."""
+    t_mfma = w["flops"] / (PEAKS[prec] * 1e12) if w["flops"] else 0.0
+    t_hbm = w["bytes"] / (HBM_PEAK * 1e9)
+    mf = {"bound": "mfma", "achieved": w["flops"] / avg_s / 1e12, "peak": PEAKS[prec],
+          "unit": "TFLOP/s", "work": w["flops"]} if w["flops"] else None
+    hb = {"bound": "hbm", "achieved": w["bytes"] / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s",
+          "work": w["bytes"]}
+    for r in (mf, hb):
+        if r:
+            r["frac"] = r["achieved"] / r["peak"]
+    main, other = (mf, hb) if t_mfma > t_hbm else (hb, mf)
+    main["other_bound"] = None if other is None else {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    main["algorithmic_time_us"] = max(t_mfma, t_hbm) * 1e6
+    return main
+
+
+TRAFFIC_TABLE = os.path.join(HERE, "profiles", "traffic_per_launch.md")
+
+
+def source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, "paper_1904_05988_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"leg_synth": ["k_legendre.hip", "mfma_ops.h", "pfsh_internal.h"],
+                  "leg_anal": ["k_legendre.hip", "mfma_ops.h", "pfsh_internal.h"],
+                  "ring": ["k_ring.hip", "mfma_ops.h", "pfsh_internal.h"],
+                  "prep": ["k_spectral.hip", "mfma_ops.h", "pfsh_internal.h"],
+                  "assemble": ["k_spectral.hip", "mfma_ops.h", "pfsh_internal.h"],
+                  "sweep_node": ["k_spectral.hip", "mfma_ops.h", "pfsh_internal.h"]}
+
+
+def measured_traffic(dom):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    table (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), if
+    the table has its (level, kernel, batch) and was taken on the kernel's
+    current source; otherwise None and the reason."""
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None, "no counter table"
+    key = f"{dom['level']}/{dom['kernel']}/b{dom['batch']}"
+    digest = source_digest(KERNEL_SOURCES[dom["kernel"]])
+    with open(TRAFFIC_TABLE) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 5 and cells[0] == f"`{key}`":
+                if cells[4].strip("`") != digest:
+                    return None, f"counters of {key} taken on another source ({cells[4]})"
+                return float(cells[2]) + float(cells[3]), f"{TRAFFIC_TABLE.split(os.sep)[-2]}/traffic_per_launch.md"
+    return None, f"no counters for {key}"
+
+
+def sht_roundtrip_benchmark(torch, pfsh, reps=20, rounds=5):
+    """The standalone batched scalar SH round trip at the fine level: 64
+    fields (16 slices x 4) of T255 synthesized to the 384 x 768 grid and
+    analysed back, FP64 and FP32 transforms; TFLOP/s on the algorithmic
+    count 2 (2 K nlat + 2.5 nlat nlon log2 nlon) per field, and the round
+    trip's error."""
+    Tf, nlf, nof, _ = FINE
+    nf = 64
+    K = (Tf + 1) * (Tf + 2) // 2
+    flops = nf * 2 * (2 * K * nlf + 2.5 * nlf * nof * math.log2(nof))
+    g = torch.Generator(device="cuda").manual_seed(7)
+    spec = torch.randn((nf, K), dtype=torch.complex128, device="cuda", generator=g)
+    spec[:, : Tf + 1] = spec[:, : Tf + 1].real
+    out = {}
+    for prec in ("fp64", "fp32"):
+        gl = pfsh.Level(Tf, nlf, nof, 3, max_batch=nf // 4, precision=prec)
+        grid = gl.sh_synthesis(spec)
+        back = gl.sh_analysis(grid)
+        err = float((back - spec).abs().max() / spec.abs().max())
+        times = []
+        for _ in range(rounds):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                gl.sh_synthesis(spec, grid)
+                gl.sh_analysis(grid, back)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b) / reps)
+        ms = float(np.median(times))
+        out[prec] = {"fields": nf, "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                     "round_trip_rel_err": err}
+        gl.close()
+    return out
+
+
 def make_block(args, mixed, n64, pfsh, inputs, torch):
     """Levels, PFASST context, arrays and the block closure for one precision
     recipe: fine transforms in `mixed` (FP64 for its last n64 iterations),
@@ -209,17 +352,27 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
             block()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = per_level = None
+        per_level = None
         if profile:
             for _, lv in named:
                 lv.profile(False)
-            # launches over the B slices (the one-off F at all nodes runs at B x nodes)
-            prof = {k: gfm.profile_read(k, batch=N_TS * MEMBERS) for k in gfm.KERNELS}
-            # every launch of every level, ms per block (event-bracketed, no graphs)
-            per_level = {}
+            # every launch of every level, ms per block (event-bracketed, no graphs),
+            # and the same split by the batch of the launch
+            per_level, groups = {}, []
+            B = N_TS * MEMBERS
             for name, lv in named:
                 d = {k: lv.profile_read(k) for k in lv.KERNELS}
                 per_level[name] = {k: round(ms / args.steps, 4) for k, (n, ms) in d.items() if n}
+                cand = sorted(set(range(1, B + 1)) | {B * lv.n_nodes})
+                for k, (n_all, _) in d.items():
+                    if not n_all:
+                        continue
+                    for b in cand:
+                        n, ms = lv.profile_read(k, batch=b)
+                        if n:
+                            groups.append({"level": name, "kernel": k, "batch": b, "launches": n,
+                                           "ms": ms})
+            per_level["_groups"] = groups
         s0 = time.perf_counter()
         for _ in range(10):
             gfm.sdc_sweep(DT, thf, fef, fif)
@@ -227,7 +380,7 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
         sweep_ms = (time.perf_counter() - s0) * 1e3 / 10
     pf.set_graphs(False)
     pf.close()
-    return dict(ms=(t1 - t0) * 1e3 / args.steps, prof=prof, per_level=per_level, sweep_ms=sweep_ms,
+    return dict(ms=(t1 - t0) * 1e3 / args.steps, per_level=per_level, sweep_ms=sweep_ms,
                 tuned=ctx["tuned"])
 
 
@@ -321,20 +474,39 @@ def rel_err_slices(a, b):
 
 
 def rel_err(a, b):
+    """Normalized max-norm error per variable; for the geopotential the mean
+    slot (0,0) (sqrt(2) Phibar) is left out of both maxima."""
     out = []
     for v in range(3):
         ref = b[:, v].copy()
+        diff = a[:, v] - b[:, v]
         if v == 0:
             ref[:, 0] = 0.0
-        out.append(float(np.abs(a[:, v] - b[:, v]).max() / np.abs(ref).max()))
+            diff[:, 0] = 0.0
+        out.append(float(np.abs(diff).max() / np.abs(ref).max()))
     return out
 
 
-def cpu_baseline(seconds_budget=20.0):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(seconds_all=15.0, seconds_one=10.0):
     """The oracle as it stands, on the host: each slice's share of one PFASST
     iteration (fine sweep, restriction, coarse F and tau, coarse F at node 0
     and coarse sweep, interpolation of the three increments, fine F at node 0),
-    for as many slices as fit the budget; scaled to iterations/s of 16 slices."""
+    for as many slices as fit the time budget, scaled to iterations/s of all
+    slices; once with the BLAS threads NumPy has (value) and once with one."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     from oracle import sdc, swe, transfer
     from paper_1904_05988_amd import inputs
     Tf, nlf, nof, nnf = FINE
@@ -342,31 +514,46 @@ def cpu_baseline(seconds_budget=20.0):
     lf, lc = swe.Level(Tf, nlf, nof), swe.Level(Tc, nlc, noc)
     sf, sc = sdc.SDC(nnf), sdc.SDC(nnc)
     x0 = initial_states(inputs)[0]
-    th, fe, fi = sdc.spread(lf, x0, nnf)
-    done, wall0, cpu0 = 0, time.perf_counter(), time.process_time()
-    while True:
-        t, e, i = sdc.sweep(lf, sf, DT, th, fe, fi)
-        tc = transfer.restrict(sf, sc, Tf, Tc, t)
-        ec = np.array([swe.explicit_rhs(lc, x) for x in tc])
-        ic = np.array([swe.implicit_rhs(lc, x) for x in tc])
-        tau = transfer.fas_tau(sf, sc, Tf, Tc, DT, e, i, ec, ic)
-        ec[0], ic[0] = swe.rhs(lc, tc[0])
-        tc2, ec2, ic2 = sdc.sweep(lc, sc, DT, tc, ec, ic, tau)
-        t = t + transfer.interpolate(sc, sf, Tc, Tf, tc2 - tc)
-        e = e + transfer.interpolate(sc, sf, Tc, Tf, ec2 - ec)
-        i = i + transfer.interpolate(sc, sf, Tc, Tf, ic2 - ic)
-        e[0], i[0] = swe.rhs(lf, t[0])
-        done += 1
-        if time.perf_counter() - wall0 > seconds_budget or done >= N_TS * MEMBERS:
-            break
-    wall = time.perf_counter() - wall0
-    cpu = time.process_time() - cpu0
-    per_slice = wall / done
     nsl = N_TS * MEMBERS
-    return {"value": 1.0 / (per_slice * nsl), "unit": "sweeps/s", "kind": "oracle",
-            "cores": max(1, int(round(cpu / wall))),
-            "sample": f"{done} of {nsl} slices' share of one PFASST iteration at T{Tf}/T{Tc} "
-                      f"({wall:.1f} s), scaled to all {nsl} slices"}
+
+    def run(budget):
+        th, fe, fi = sdc.spread(lf, x0, nnf)
+        done, wall0, cpu0 = 0, time.perf_counter(), time.process_time()
+        while True:
+            t, e, i = sdc.sweep(lf, sf, DT, th, fe, fi)
+            tc = transfer.restrict(sf, sc, Tf, Tc, t)
+            ec = np.array([swe.explicit_rhs(lc, x) for x in tc])
+            ic = np.array([swe.implicit_rhs(lc, x) for x in tc])
+            tau = transfer.fas_tau(sf, sc, Tf, Tc, DT, e, i, ec, ic)
+            ec[0], ic[0] = swe.rhs(lc, tc[0])
+            tc2, ec2, ic2 = sdc.sweep(lc, sc, DT, tc, ec, ic, tau)
+            t = t + transfer.interpolate(sc, sf, Tc, Tf, tc2 - tc)
+            e = e + transfer.interpolate(sc, sf, Tc, Tf, ec2 - ec)
+            i = i + transfer.interpolate(sc, sf, Tc, Tf, ic2 - ic)
+            e[0], i[0] = swe.rhs(lf, t[0])
+            done += 1
+            if time.perf_counter() - wall0 > budget or done >= nsl:
+                break
+        return done, time.perf_counter() - wall0, time.process_time() - cpu0
+
+    blas = [{"api": d.get("internal_api"), "version": d.get("version"),
+             "threads": d.get("num_threads")} for d in threadpool_info() if d.get("user_api") == "blas"]
+    threads = max([d["threads"] or 1 for d in blas] or [1])
+    done, wall, cpu = run(seconds_all)
+    with threadpool_limits(limits=1):
+        done1, wall1, _ = run(seconds_one)
+    sample = (f"{{}} of {nsl} slices' share of one PFASST iteration at T{Tf}/T{Tc} ({{:.1f}} s), "
+              f"scaled to all {nsl} slices")
+    runs = {"all_threads": {"value": done / (wall * nsl), "unit": "sweeps/s", "cores": threads,
+                            "sample": sample.format(done, wall), "cpu_time_over_wall": cpu / wall},
+            "single_thread": {"value": done1 / (wall1 * nsl), "unit": "sweeps/s", "cores": 1,
+                              "sample": sample.format(done1, wall1)}}
+    # the headline figure is the faster of the two settings (NumPy's many small
+    # matrix products can run slower on many BLAS threads than on one)
+    best = max(runs.values(), key=lambda r: r["value"])
+    return {"value": best["value"], "unit": "sweeps/s", "kind": "oracle", "cores": best["cores"],
+            "sample": best["sample"], "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "blas": blas, "runs": runs}
 
 
 def main():
@@ -432,75 +619,40 @@ def main():
     xref = serial_reference(torch, pfsh, inputs)
     sweeps = sweep_benchmark(torch, pfsh, inputs)
 
-    # dominant kernel of the mixed-precision fine level and its roofline
-    prof = rpr["prof"]
+    # the kernel with the largest time per block over all levels and batches,
+    # and every (level, kernel, batch) group against its own bound
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
     B = N_TS * MEMBERS
-    rsz = 8 if args.mixed == "fp64" else 4
-
-    def kernel_work(k):
-        """(bound, algorithmic work per launch at batch B) of a fine-level kernel"""
-        if k in ("leg_synth", "leg_anal"):
-            return "mfma", legendre_flops(Tf, nlf, (8 if k == "leg_synth" else 10) * B)
-        if k == "ring":
-            return "hbm", ring_bytes(Tf, nlf, rsz, B)
-        if k == "sweep_node":
-            return "hbm", sweep_node_bytes(Tf, nnf, B, rsz)
-        return None, None
-
-    # the dominant kernel among those with a work model and launches over all B
-    # slices (the wavefront schedule sweeps smaller groups of slices: then none)
-    cands = [k for k in prof if kernel_work(k)[0] and prof[k][0] > 0 and prof[k][1] > 0]
-    if not cands:
-        dom = None
-        roof = {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None, "note": f"no launch over all {B} slices in this schedule"}
-    else:
-        dom = max(cands, key=lambda k: prof[k][1])
-        n, tot = prof[dom]
-        avg_s = tot / n * 1e-3
-        bound, work = kernel_work(dom)
-        if bound == "mfma":
-            roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAKS[args.mixed],
-                    "unit": "TFLOP/s"}
-        else:
-            roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counters of these kernel
-    # versions (reads x2, writes x1 after calibration against a plain copy), FP32
-    # fine level at T255 over 16 slices, per tuner variant (the tuner may keep
-    # another one from run to run: then none); the sweep node is averaged over
-    # nodes 1-4
-    measured = {("sweep_node", "fp32", 255, 16, None): 280.71e6,
-                ("ring", "fp32", 255, 16, 0): 114.56e6,
-                ("leg_synth", "fp32", 255, 16, 0): 108.03e6,
-                ("leg_synth", "fp32", 255, 16, 3): 101.47e6,
-                ("leg_anal", "fp32", 255, 16, 0): 115.59e6,
-                ("leg_anal", "fp32", 255, 16, 6): 117.41e6}
-    stage_of = {"leg_synth": "synth", "leg_anal": "anal", "ring": "ring"}
-    if dom is not None:
-        var = rmx["tuned"].get("fine", {}).get(B, {}).get(stage_of.get(dom)) if dom in stage_of else None
-        roof["traffic"] = measured.get((dom, args.mixed, Tf, B, var))   # HBM bytes per launch (measured)
-        roof["variant"] = var
-        roof["algorithmic_per_launch"] = work       # bytes (hbm) or flops (mfma) per launch
-        roof["kernel"] = dom
-        roof["launches"] = n
-        roof["avg_us"] = avg_s * 1e6
-
-    # every transform stage of the fine level against its own bound
-    stages = {}
-    for k, (cnt, tot_ms) in prof.items():
-        bnd, w = kernel_work(k)
-        if cnt == 0 or bnd is None:
+    geom = {"fine": (FINE, args.mixed), "fine_fp64": (FINE, "fp64"), "coarse": (COARSE, "fp64")}
+    groups = []
+    for g in rpr["per_level"].pop("_groups"):
+        (T, nlat, nlon, nn), prec = geom[g["level"]]
+        w = kernel_work(g["kernel"], T, nlat, nlon, nn, g["batch"], prec)
+        if w is None:
             continue
-        sec = tot_ms / cnt * 1e-3
-        if bnd == "mfma":
-            stages[k] = {"bound": "mfma", "tflops": w / sec / 1e12,
-                         "frac": w / sec / 1e12 / PEAKS[args.mixed], "avg_us": sec * 1e6}
-        else:
-            stages[k] = {"bound": "hbm", "gbs": w / sec / 1e9, "frac": w / sec / 1e9 / HBM_PEAK,
-                         "avg_us": sec * 1e6}
+        avg_s = g["ms"] / g["launches"] * 1e-3
+        r = roofline_of(w, avg_s, prec)
+        r.update({"level": g["level"], "kernel": g["kernel"], "symbol": w["symbol"],
+                  "batch": g["batch"], "launches_per_block": g["launches"] / args.steps,
+                  "ms_per_block": g["ms"] / args.steps, "avg_us": avg_s * 1e6})
+        groups.append(r)
+    groups.sort(key=lambda r: -r["ms_per_block"])
+    if groups:
+        dom = groups[0]
+        roof = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+        roof["traffic"], roof["traffic_source"] = measured_traffic(dom)
+        roof.update({k: dom[k] for k in ("level", "kernel", "symbol", "batch", "avg_us",
+                                         "launches_per_block", "ms_per_block")})
+        roof["algorithmic_per_launch"] = dom["work"]
+        roof["other_bound"] = dom["other_bound"]
+    else:
+        roof = {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "note": "no profiled launch"}
+    stages = {f"{r['level']}/{r['kernel']}/b{r['batch']}":
+              {k: r[k] for k in ("bound", "achieved", "unit", "frac", "avg_us", "ms_per_block")}
+              for r in groups[:12]}
+    sht_rt = sht_roundtrip_benchmark(torch, pfsh)
     sht = block_sht_flops(FINE, COARSE, N_TS, args.n_pf, MEMBERS)
     value = args.n_pf * 1e3 / rmx["ms"]
     out = {
@@ -517,6 +669,7 @@ def main():
                    "seeds": list(SEEDS), "parallelism": "slices x members as batch, 1 GPU"},
         "roofline": roof,
         "stage_fractions": stages,
+        "sht_roundtrip": sht_rt,
         "fp64": {"sweeps_per_s": args.n_pf * 1e3 / r64["ms"], "ms_per_step": r64["ms"],
                  "sweep_only_ms": r64["sweep_ms"],
                  "sht_tflops": sht / (r64["ms"] * 1e-3) / 1e12},
@@ -531,7 +684,6 @@ def main():
         "sweep_only_ms": rmx["sweep_ms"],
         "sweep_benchmark": sweeps,
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
-        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
         "kernel_ms_per_step_all_levels": rpr["per_level"],
         "tuned_variants": rmx["tuned"],
     }
