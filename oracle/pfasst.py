@@ -75,8 +75,9 @@ def _eval_all(lv, th, lin):
     return fe, fi
 
 
-def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False):
-    """PFASST(n_ts, Mf+1, Mc+1, n_iter) over one block starting at theta0 [3, Kf]."""
+def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False, misdc=False):
+    """PFASST(n_ts, Mf+1, Mc+1, n_iter) over one block starting at theta0 [3, Kf];
+    misdc: every sweep takes the two-substep implicit step (sdc.sweep)."""
     Tf, Tc = lv_f.T, lv_c.T
     lin = linear_coriolis
     mb = Mailbox()
@@ -99,7 +100,8 @@ def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False)
                 new_ic = mb.recv(("pred", stage - 1, n - 1))
                 th_c[n][0] = new_ic
                 fe_c[n][0], fi_c[n][0] = swe.rhs(lv_c, new_ic, lin)
-            th_c[n], fe_c[n], fi_c[n] = sdc.sweep(lv_c, sd_c, dt, th_c[n], fe_c[n], fi_c[n], None, lin)
+            th_c[n], fe_c[n], fi_c[n] = sdc.sweep(lv_c, sd_c, dt, th_c[n], fe_c[n], fi_c[n], None, lin,
+                                                  misdc)
         for n in range(stage, n_ts):
             mb.send(("pred", stage, n), th_c[n][-1])
     fe_f, fi_f = [], []
@@ -113,7 +115,8 @@ def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False)
     for k in range(n_iter):
         # A) fine sweeps
         for n in range(n_ts):
-            th_f[n], fe_f[n], fi_f[n] = sdc.sweep(lv_f, sd_f, dt, th_f[n], fe_f[n], fi_f[n], None, lin)
+            th_f[n], fe_f[n], fi_f[n] = sdc.sweep(lv_f, sd_f, dt, th_f[n], fe_f[n], fi_f[n], None, lin,
+                                                  misdc)
         res.end_values.append(np.array([th_f[n][-1] for n in range(n_ts)]))
         if k == n_iter - 1:
             break
@@ -132,7 +135,8 @@ def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False)
                 new_ic = mb.recv(("coarse", k, n - 1))
                 th_c[n][0] = new_ic
                 fe_c[n][0], fi_c[n][0] = swe.rhs(lv_c, new_ic, lin)
-            th_c[n], fe_c[n], fi_c[n] = sdc.sweep(lv_c, sd_c, dt, th_c[n], fe_c[n], fi_c[n], tau[n], lin)
+            th_c[n], fe_c[n], fi_c[n] = sdc.sweep(lv_c, sd_c, dt, th_c[n], fe_c[n], fi_c[n], tau[n], lin,
+                                                  misdc)
             if n < n_ts - 1:
                 mb.send(("coarse", k, n), th_c[n][-1])
         # D) interpolate increments, new fine initial condition

@@ -115,9 +115,18 @@ def spread(lv, theta0, nnodes, linear_coriolis=False):
     return th, np.repeat(fe[None], nnodes, axis=0), np.repeat(fi[None], nnodes, axis=0)
 
 
-def sweep(lv, sd, dt, theta, fe, fi, tau=None, linear_coriolis=False):
+def sweep(lv, sd, dt, theta, fe, fi, tau=None, linear_coriolis=False, misdc=False):
     """One IMEX SDC sweep.  theta/fe/fi: [M+1, 3, K]; node 0 is the initial
-    condition with its F already evaluated.  Returns new (theta, fe, fi)."""
+    condition with its F already evaluated.  Returns new (theta, fe, fi).
+
+    misdc: the implicit step of each node in two substeps (Sec. 5.1.1, last
+    paragraph; the multi-implicit form of the cited Bourlioux et al. work):
+    with F_I = L1 Theta + L2 Theta (physical linear terms, diffusion),
+      Theta* = (I - beta L1)^{-1} (b + beta L2 Theta^{m+1,(k)}),
+      Theta^{m+1,(k+1)} = (I - beta L2)^{-1} (Theta* - beta L2 Theta^{m+1,(k)}),
+    beta = dt qI_{m+1,m+1}: each substep is implicit in its own part, and the
+    old value of the other part stands in for it, so the fixed point is the
+    same collocation solution."""
     M = sd.M
     th_new, fe_new, fi_new = theta.copy(), fe.copy(), fi.copy()
     ftot = fe + fi
@@ -132,7 +141,13 @@ def sweep(lv, sd, dt, theta, fe, fi, tau=None, linear_coriolis=False):
             b += dt * sd.Q[m + 1, j] * ftot[j]
         if tau is not None:
             b += tau[m + 1]
-        x = swe.implicit_solve(lv, dt * sd.QI[m + 1, m + 1], b)
+        beta = dt * sd.QI[m + 1, m + 1]
+        if misdc:
+            f2_old = swe.diffusion_rhs(lv, theta[m + 1])
+            x_star = swe.gravity_solve(lv, beta, b + beta * f2_old)
+            x = swe.diffusion_solve(lv, beta, x_star - beta * f2_old)
+        else:
+            x = swe.implicit_solve(lv, beta, b)
         th_new[m + 1] = x
         fi_new[m + 1] = swe.implicit_rhs(lv, x)
         fe_new[m + 1] = swe.explicit_rhs(lv, x, linear_coriolis)
@@ -159,12 +174,12 @@ def residual_norm(sd, dt, theta, fe, fi, tau=None):
     return np.abs(r).max(axis=(0, 2))
 
 
-def serial_sdc(lv, sd, dt, theta0, nsteps, nsweeps, linear_coriolis=False):
+def serial_sdc(lv, sd, dt, theta0, nsteps, nsweeps, linear_coriolis=False, misdc=False):
     """SDC(M+1, N_S) time stepping (spread guess, N_S sweeps per step)."""
     th0 = theta0.copy()
     for _ in range(nsteps):
         th, fe, fi = spread(lv, th0, sd.M + 1, linear_coriolis)
         for _ in range(nsweeps):
-            th, fe, fi = sweep(lv, sd, dt, th, fe, fi, None, linear_coriolis)
+            th, fe, fi = sweep(lv, sd, dt, th, fe, fi, None, linear_coriolis, misdc)
         th0 = th[-1].copy()
     return th0

@@ -83,6 +83,41 @@ def implicit_solve(lv, beta, b):
     return x
 
 
+# The two parts of L for the two-substep (multi-implicit) variant of the
+# implicit step (Sec. 5.1.1, last paragraph): L = L1 + L2 with L1 the physical
+# linear terms (gravity waves) and L2 the artificial diffusion nu lap.
+def gravity_rhs(lv, theta):
+    """L1 Theta: (-Phibar delta, 0, -lam Phi) per mode."""
+    p = lv.phys
+    out = np.zeros_like(theta)
+    out[0] = -p.phibar * theta[2]
+    out[2] = -lv.lam * theta[0]
+    return out
+
+
+def diffusion_rhs(lv, theta):
+    """L2 Theta = nu lam_n Theta per mode and variable."""
+    return lv.phys.nu * lv.lam * theta
+
+
+def gravity_solve(lv, beta, b):
+    """Solve (I - beta L1) x = b: zeta unchanged, a 2x2 system for (Phi, delta)
+    with det = 1 - beta^2 Phibar lam."""
+    p = lv.phys
+    lam = lv.lam
+    det = 1.0 - beta * beta * p.phibar * lam
+    x = np.empty_like(b)
+    x[1] = b[1]
+    x[0] = (b[0] - beta * p.phibar * b[2]) / det
+    x[2] = (b[2] - beta * lam * b[0]) / det
+    return x
+
+
+def diffusion_solve(lv, beta, b):
+    """Solve (I - beta L2) x = b: x = b / (1 - beta nu lam) per mode."""
+    return b / (1.0 - beta * lv.phys.nu * lv.lam)
+
+
 # ------------------------------------------------------------ nonlinear part
 def streamfunction(lv, field):
     """psi = lap^{-1} zeta (likewise chi from delta): -a^2/(n(n+1)) per mode, 0 at n=0."""
