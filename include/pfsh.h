@@ -139,6 +139,21 @@ pfsh_status pfsh_implicit_solve(pfsh_level* level, double beta, const void* b, v
 pfsh_status pfsh_sdc_sweep(pfsh_level* level, double dt, void* theta, void* f_expl, void* f_impl,
                            const void* tau, int batch, void* stream);
 
+/* Form of the implicit step of every sweep on the level (Sec. 5.1.1, last
+ * paragraph).  PFSH_IMPLICIT_COMBINED (the default): one solve
+ * (I - beta L) Theta = b per node and mode, as eq.
+ * update_equation_sdcq_discrete_form is written.  PFSH_IMPLICIT_SPLIT: two
+ * substeps as in the paper's implementation (multi-implicit SDC): with
+ * L = L1 + L2, L1 the physical linear terms (-Phibar delta, 0, -lap Phi) and L2
+ * = nu lap, Theta* = (I - beta L1)^{-1} (b + beta L2 Theta_old) and then
+ * Theta = (I - beta L2)^{-1} (Theta* - beta L2 Theta_old), Theta_old the
+ * previous iterate at the node, beta = dt qI_{m+1,m+1}; the same collocation
+ * fixed point.  Host-only; affects sweeps enqueued (or graphs captured) after
+ * the call.  PFSH_EINVAL for another mode. */
+#define PFSH_IMPLICIT_COMBINED 0
+#define PFSH_IMPLICIT_SPLIT 1
+pfsh_status pfsh_level_set_implicit(pfsh_level* level, int mode);
+
 /* Collocation residual (Sec. 5.1.1, eq. collocation_problem; FAS form of
  * Sec. 5.1.2 when tau != NULL): r^m = theta^0 + dt (Q F)_m + tau^m - theta^m.
  * out [batch][3] float64 (device) receives max over nodes and modes of |r|

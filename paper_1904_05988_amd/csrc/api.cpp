@@ -166,6 +166,12 @@ extern "C" pfsh_status pfsh_sdc_sweep(pfsh_level* lv, double dt, void* theta, vo
                           (const double*)tau, batch, (hipStream_t)stream));
 }
 
+extern "C" pfsh_status pfsh_level_set_implicit(pfsh_level* lv, int mode) {
+  if (!lv || (mode != PFSH_IMPLICIT_COMBINED && mode != PFSH_IMPLICIT_SPLIT)) return PFSH_EINVAL;
+  lv->implicit_split = mode == PFSH_IMPLICIT_SPLIT ? 1 : 0;
+  return PFSH_OK;
+}
+
 extern "C" pfsh_status pfsh_residual(pfsh_level* lv, double dt, const void* theta,
                                      const void* f_expl, const void* f_impl, const void* tau,
                                      double* out, int batch, void* stream) {

@@ -292,6 +292,7 @@ __global__ void k_implicit_solve(const double* __restrict__ bv, double* __restri
 struct SdcMat {
   double Q[81], QE[81], QI[81];
   int nn;
+  int split;   // implicit step in two substeps (physical linear, then diffusion)
 };
 
 // Node-0 values received from elsewhere (state, F_E, F_I), as raw pointers;
@@ -422,7 +423,31 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
     }
     rhs[v] = r;
   }
-  solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], x[0], x[1], x[2]);
+  if (sm.split) {
+    // Two substeps (Sec. 5.1.1, last paragraph): L = L1 + L2 with L1 the
+    // physical linear terms and L2 = nu lap.  Theta* = (I - beta L1)^{-1}
+    // (b + beta L2 Theta_old), then Theta = (I - beta L2)^{-1} (Theta* - beta
+    // L2 Theta_old), Theta_old the previous iterate at this node.
+    C2 o[3], bs[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) o[v] = ld2(th + 2 * (base + ((size_t)node * 3 + v) * K + k));
+    const double dl = ph.nu * lam;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      o[v] = {dl * o[v].x, dl * o[v].y};                       // L2 Theta_old
+      bs[v] = {rhs[v].x + beta * o[v].x, rhs[v].y + beta * o[v].y};
+    }
+    const double det = 1.0 - beta * beta * ph.phibar * lam, idet = 1.0 / det;
+    const C2 s0 = {(bs[0].x - beta * ph.phibar * bs[2].x) * idet, (bs[0].y - beta * ph.phibar * bs[2].y) * idet};
+    const C2 s2 = {(bs[2].x - beta * lam * bs[0].x) * idet, (bs[2].y - beta * lam * bs[0].y) * idet};
+    const C2 xs[3] = {s0, bs[1], s2};
+    const double id = 1.0 / (1.0 - beta * dl);
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+      x[v] = {(xs[v].x - beta * o[v].x) * id, (xs[v].y - beta * o[v].y) * id};
+  } else {
+    solve_mode(lam, beta, ph, rhs[0], rhs[1], rhs[2], x[0], x[1], x[2]);
+  }
   C2 f[3];
   linear_mode(lam, ph, x[0], x[1], x[2], f);
   for (int v = 0; v < 3; ++v) {
@@ -957,6 +982,7 @@ static inline SdcMat sdc_of(const pfsh_level* lv) {
   SdcMat s;
   for (int i = 0; i < 81; ++i) { s.Q[i] = lv->Q[i]; s.QE[i] = lv->QE[i]; s.QI[i] = lv->QI[i]; }
   s.nn = lv->nn;
+  s.split = lv->implicit_split;
   return s;
 }
 

@@ -128,6 +128,7 @@ struct pfsh_level {
   size_t red_len = 0;
   size_t bytes_tables = 0, bytes_work = 0;
   unsigned char variant[pfsh::TS_COUNT][pfsh::kTuneBuckets] = {};   // chosen kernel variants
+  int implicit_split = 0;  // sweeps: implicit step in two substeps (pfsh_level_set_implicit)
   // diagnostic kernel timing (pfsh_profile_*)
   mutable bool prof_on = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[PFSH_K_COUNT];

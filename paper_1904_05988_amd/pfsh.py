@@ -49,6 +49,7 @@ _SIGS = {
     "pfsh_sdc_sweep": ([_P, _D, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_residual": ([_P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
     "pfsh_residual_noalloc": ([_P, _D, _P, _P, _P, _P, _P, _I, _P], _I),
+    "pfsh_level_set_implicit": ([_P, _I], _I),
     "pfsh_check_finite": ([_P, _I, _P], _I),
     "pfsh_spread": ([_P, _P, _P, _P, _I, _P], _I),
     "pfsh_restrict": ([_P, _P, _P, _P, _I, _P], _I),
@@ -164,6 +165,13 @@ class Level:
             self.close()
         except Exception:
             pass
+
+    IMPLICIT = {"combined": 0, "split": 1}
+
+    def set_implicit(self, mode):
+        """Implicit step of the level's sweeps: "combined" (one solve with L)
+        or "split" (physical linear substep, then diffusion substep)."""
+        _check(lib().pfsh_level_set_implicit(self._h, self.IMPLICIT[mode]), "pfsh_level_set_implicit")
 
     # -- diagnostic kernel timing
     KERNELS = {"leg_synth": 0, "ring": 1, "leg_anal": 2, "assemble": 3, "prep": 4,

@@ -80,6 +80,8 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.pfsh_sh_synthesis(None, one, one, 1, None) == -1
     assert L.pfsh_sh_analysis(None, one, one, 1, None) == -1
     assert L.pfsh_residual(None, 1.0, one, one, one, None, one, 1, None) == -1
+    assert L.pfsh_residual_noalloc(None, 1.0, one, one, one, None, one, 1, None) == -1
+    assert L.pfsh_level_set_implicit(None, 0) == -1
     assert L.pfsh_restrict(None, None, one, one, 1, None) == -1
     assert L.pfsh_interpolate_add(None, None, one, None, one, 1, None) == -1
     assert L.pfsh_fas_tau(None, None, 1.0, one, one, one, one, one, 1, None) == -1
