@@ -65,6 +65,8 @@ class PfasstResult:
         self.end_values = []       # per iteration: [n_ts, 3, Kf] fine last-node values after step A
         self.pred_end = None       # [n_ts, 3, Kf] fine last-node values after the predictor
         self.after_iter = []       # per non-final iteration: [n_ts, Mf+1, 3, Kf] fine state after D
+        self.residuals = []        # per iteration: [n_ts, 3] fine residual norms after step A
+        self.iterations = 0        # iterations performed
 
 
 def _eval_all(lv, th, lin):
@@ -75,9 +77,17 @@ def _eval_all(lv, th, lin):
     return fe, fi
 
 
-def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False, misdc=False):
+def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False, misdc=False,
+        tol=None):
     """PFASST(n_ts, Mf+1, Mc+1, n_iter) over one block starting at theta0 [3, Kf];
-    misdc: every sweep takes the two-substep implicit step (sdc.sweep)."""
+    misdc: every sweep takes the two-substep implicit step (sdc.sweep).
+
+    tol (three per-variable bounds, or None): the convergence check the paper
+    leaves to future work (Sec. 5.2.2).  After the fine sweep of every
+    iteration, the collocation residual of each time step (max over nodes and
+    modes, per variable) is taken; when it is at most tol for every step and
+    variable, that iteration stops after its fine sweep, as the last one does.
+    n_iter is then the largest number of iterations."""
     Tf, Tc = lv_f.T, lv_c.T
     lin = linear_coriolis
     mb = Mailbox()
@@ -118,7 +128,10 @@ def run(lv_f, lv_c, sd_f, sd_c, dt, theta0, n_ts, n_iter, linear_coriolis=False,
             th_f[n], fe_f[n], fi_f[n] = sdc.sweep(lv_f, sd_f, dt, th_f[n], fe_f[n], fi_f[n], None, lin,
                                                   misdc)
         res.end_values.append(np.array([th_f[n][-1] for n in range(n_ts)]))
-        if k == n_iter - 1:
+        r = np.array([sdc.residual_norm(sd_f, dt, th_f[n], fe_f[n], fi_f[n]) for n in range(n_ts)])
+        res.residuals.append(r)
+        res.iterations = k + 1
+        if k == n_iter - 1 or (tol is not None and np.all(r <= np.asarray(tol)[None, :])):
             break
         for n in range(n_ts - 1):
             mb.send(("fine", k, n), th_f[n][-1])

@@ -129,3 +129,27 @@ def test_pfasst_single_slice_is_two_level_iteration(levels):
     res = pfasst.run(lf, lc, s5, s3, 300.0, th0, 1, 12)
     for v in range(3):
         assert np.abs(res.end_values[-1][0, v] - ref[0, v]).max() <= 1e-12 * np.abs(ref[0, v]).max()
+
+
+def test_residual_stop_equals_fixed_iterations(levels):
+    """The convergence check (future work of Sec. 5.2.2, reading: stop after
+    the fine sweep of the first iteration whose fine collocation residuals are
+    at most tol for every time step and variable) stops where the residual
+    history first falls below tol, with the state of the fixed-iteration run
+    of that many iterations, bit for bit; without tol all iterations run."""
+    lf, lc = levels
+    sf, sc = sdc.SDC(5), sdc.SDC(3)
+    th0 = inputs.seeded_state(TF, 21)
+    full = pfasst.run(lf, lc, sf, sc, 200.0, th0, 4, 8)
+    assert full.iterations == 8 and len(full.residuals) == 8
+    hist = np.array([r.max(axis=0) for r in full.residuals])       # [iteration, var]
+    for v in range(3):
+        assert hist[-1, v] < 1e-3 * hist[0, v], hist[:, v]           # the iteration converges
+    tol = hist[3] * 1.01                       # met by the 4th iteration's residuals (or earlier)
+    first = next(i for i in range(8) if np.all(hist[i] <= tol)) + 1
+    assert first <= 4
+    stopped = pfasst.run(lf, lc, sf, sc, 200.0, th0, 4, 8, tol=tol)
+    assert stopped.iterations == first
+    fixed = pfasst.run(lf, lc, sf, sc, 200.0, th0, 4, first)
+    np.testing.assert_array_equal(stopped.end_values[-1], fixed.end_values[-1])
+    np.testing.assert_array_equal(np.array(stopped.theta), np.array(fixed.theta))
