@@ -337,6 +337,44 @@ pfsh_status pfsh_pfasst_iterate(pfsh_pfasst* ctx, double dt, void* theta_f, void
 pfsh_status pfsh_pfasst_run(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
                             int n_iter, pfsh_level* fine_alt, int k_switch, void* stream);
 
+/* PFASST iterations with a convergence check, the variant the paper leaves to
+ * future work (Sec. 5.2.2): after the fine sweep (step A) of every iteration
+ * the fine collocation residual of every slice is taken (pfsh_residual: max
+ * over nodes and modes, per variable) and copied to the host; when it is at
+ * most tol[v] (host, 3 absolute bounds for Phi, zeta, delta) for every slice
+ * and variable, or when max_iter iterations have run, the iteration stops
+ * there, after its fine sweep, as the last iteration of pfsh_pfasst_iterate
+ * does; otherwise steps B-D follow.  Synchronizes the stream once per
+ * iteration; direct launches (no graph replay).  iterations (host, nullable)
+ * receives the number of iterations performed, residuals (host, nullable,
+ * [max_iter][n_ts*members][3]) the residuals after each fine sweep.
+ * PFSH_ENONFINITE when a residual is NaN/Inf (the iteration stops there). */
+pfsh_status pfsh_pfasst_run_tol(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
+                                int max_iter, const double* tol, int* iterations, double* residuals,
+                                void* stream);
+
+/* Serial comparators of Sec. 5.5 on the same kernels.
+ *
+ * pfsh_sdc_run: SDC(M+1, nsweeps) over nsteps time steps of dt for `batch`
+ * independent states.  theta, f_expl, f_impl [batch][n_nodes][3][K]: on entry
+ * node 0 of theta holds the initial states (the other entries are work
+ * space); each step evaluates F at node 0, spreads state and F to every node
+ * (the spread initial iterate), runs nsweeps sweeps and moves the last node to
+ * node 0.  On return node 0 (and the last node) hold the states after nsteps
+ * steps.
+ *
+ * pfsh_mlsdc_run: MLSDC(Mf+1, Mc+1, n_iter, alpha) over nsteps steps with the
+ * levels of a PFASST context created with n_ts = 1 (members = the batch; else
+ * PFSH_ESHAPE).  Each step starts as above on the fine level and runs n_iter
+ * iterations of one fine sweep, the restriction, coarse F at all coarse nodes
+ * and tau, one coarse FAS sweep from the restricted initial condition, and the
+ * interpolated increments of Theta, F_E, F_I at all fine nodes (Algorithm 1 on
+ * one time step); fine arrays and return as pfsh_sdc_run. */
+pfsh_status pfsh_sdc_run(pfsh_level* level, double dt, void* theta, void* f_expl, void* f_impl,
+                         int nsteps, int nsweeps, int batch, void* stream);
+pfsh_status pfsh_mlsdc_run(pfsh_pfasst* ctx, double dt, void* theta_f, void* fe_f, void* fi_f,
+                           int nsteps, int n_iter, void* stream);
+
 /* Swap the context's fine and coarse levels for levels of the same geometry
  * (T, nlat, nlon, n_nodes, device; max_batch large enough), e.g. levels of
  * another transform precision: later calls use the new levels, the state

@@ -3,6 +3,7 @@
 // the sends and receives of the algorithm are device copies along the batch
 // axis; the coarse step C stays a serial chain over time steps.
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -25,6 +26,7 @@ struct pfsh_pfasst {
   double* snap = nullptr;  // fine last-node values sent in step A [B][3][Kf]
   double* fmail = nullptr; // wavefront: fine last-node values, two super-steps [2][B][3][Kf]
   double* cmail = nullptr; // wavefront: coarse last-node state, F_E, F_I [2][B][3][3][Kc]
+  double* res = nullptr;   // fine residual per slice and variable [B][3] (pfsh_pfasst_run_tol)
   bool graphs = false;     // replay captured iterations
   struct Cached {
     const void *thf, *fef, *fif;
@@ -58,7 +60,7 @@ void drop_graphs(pfsh_pfasst* x) {
 void free_ctx(pfsh_pfasst* x) {
   drop_graphs(x);
   double* p[] = {x->thc, x->fec, x->fic, x->tthc, x->tfec, x->tfic, x->tau, x->base, x->snap,
-                 x->fmail, x->cmail};
+                 x->fmail, x->cmail, x->res};
   for (double* q : p)
     if (q) (void)hipFree(q);
   delete x;
@@ -128,13 +130,11 @@ hipError_t predict(pfsh_pfasst* x, double dt, const double* th0, double* thf, do
   return eval_all(x->f, thf, fef, fif, B, s);
 }
 
-hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* fif, bool last,
-                   hipStream_t s) {
+// Steps B-D of an iteration (after its fine sweep, step A).
+hipError_t iterate_bd(pfsh_pfasst* x, double dt, double* thf, double* fef, double* fif,
+                      hipStream_t s) {
   const Sizes z = sizes(x);
   const int mem = x->members, B = x->B, Mf = x->f->M, Mc = x->c->M;
-  // A) fine sweep of all steps
-  PF_TRY(sweep_impl(x->f, dt, thf, fef, fif, nullptr, B, s));
-  if (last) return hipSuccess;
   PF_TRY(launch_copy_state(thf + 2 * (size_t)Mf * z.n3kf, z.stf, x->snap, z.n3kf, z.n3kf, B, s));
   // B) restrict, coarse F, saved copies, tau
   PF_TRY(launch_restrict(x->f, x->c, thf, x->thc, B, s));
@@ -169,10 +169,38 @@ hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* 
     double* io[3] = {thf, fef, fif};
     PF_TRY(launch_interp_add3(x->c, x->f, 3, nw, od, io, B, s));
   }
-  if (x->n_ts > 1)
-    PF_TRY(launch_ic_correct(x->f, x->c, x->snap, z.n3kf, x->thc + 2 * (size_t)mem * z.stc, z.stc,
-                             thf + 2 * (size_t)mem * z.stf, z.stf, B - mem, s));
+  // (one time step per block: no initial condition changes, and the
+  // interpolated node-0 increment is exactly zero, so F there stands)
+  if (x->n_ts == 1) return hipSuccess;
+  PF_TRY(launch_ic_correct(x->f, x->c, x->snap, z.n3kf, x->thc + 2 * (size_t)mem * z.stc, z.stc,
+                           thf + 2 * (size_t)mem * z.stf, z.stf, B - mem, s));
   return rhs_strided(x->f, thf, z.stf, fef, z.stf, fif, z.stf, B, s);
+}
+
+// Node 0 of every slice from the state there: F at node 0, then state and F
+// copied to every node (spread initial iterate).
+hipError_t start_step(const pfsh_level* lv, double* th, double* fe, double* fi, int batch,
+                      hipStream_t s) {
+  const long long st = lv->nn * 3LL * lv->K;
+  PF_TRY(rhs_strided(lv, th, st, fe, st, fi, st, batch, s));
+  PF_TRY(launch_spread(lv, th, batch, s));
+  PF_TRY(launch_spread(lv, fe, batch, s));
+  return launch_spread(lv, fi, batch, s);
+}
+
+// The last node's state of every slice to node 0 (the next step's initial
+// condition).
+hipError_t next_step(const pfsh_level* lv, double* th, int batch, hipStream_t s) {
+  const long long n3k = 3LL * lv->K, st = lv->nn * n3k;
+  return launch_copy_state(th + 2 * (size_t)lv->M * n3k, st, th, st, n3k, batch, s);
+}
+
+hipError_t iterate(pfsh_pfasst* x, double dt, double* thf, double* fef, double* fif, bool last,
+                   hipStream_t s) {
+  // A) fine sweep of all steps
+  PF_TRY(sweep_impl(x->f, dt, thf, fef, fif, nullptr, x->B, s));
+  if (last) return hipSuccess;
+  return iterate_bd(x, dt, thf, fef, fif, s);
 }
 
 // n_iter iterations in wavefront order.  Super-step t advances every step n
@@ -299,6 +327,7 @@ extern "C" pfsh_status pfsh_pfasst_create(pfsh_level* f, pfsh_level* c, int n_ts
   if (e == hipSuccess) e = hipMalloc((void**)&x->snap, bf);
   if (e == hipSuccess) e = hipMalloc((void**)&x->fmail, 2 * bf);
   if (e == hipSuccess) e = hipMalloc((void**)&x->cmail, 2 * (size_t)B * 3 * z.n3kc * 16);
+  if (e == hipSuccess) e = hipMalloc((void**)&x->res, (size_t)B * 3 * sizeof(double));
   if (e == hipSuccess)
     for (double** p : bufs)
       if (e == hipSuccess) e = hipMemset(*p, 0, bc);
@@ -453,4 +482,101 @@ extern "C" pfsh_status pfsh_pfasst_set_graphs(pfsh_pfasst* x, int on) {
   }
   x->graphs = on != 0;
   return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_pfasst_run_tol(pfsh_pfasst* x, double dt, void* theta_f, void* fe_f,
+                                           void* fi_f, int max_iter, const double* tol,
+                                           int* iterations, double* residuals, void* stream) {
+  if (iterations) *iterations = 0;
+  if (!x || !theta_f || !fe_f || !fi_f || !tol) return PFSH_EINVAL;
+  if (!(dt > 0) || max_iter < 1) return PFSH_EINVAL;
+  for (int v = 0; v < 3; ++v)
+    if (!(tol[v] >= 0)) return PFSH_EINVAL;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(x->f->device);
+  hipStream_t s = (hipStream_t)stream;
+  double* thf = (double*)theta_f;
+  double* fef = (double*)fe_f;
+  double* fif = (double*)fi_f;
+  std::vector<double> r((size_t)x->B * 3);
+  pfsh_status st = PFSH_OK;
+  for (int k = 0; k < max_iter; ++k) {
+    // A) fine sweep, then the fine collocation residual of every slice
+    hipError_t e = sweep_impl(x->f, dt, thf, fef, fif, nullptr, x->B, s);
+    if (e == hipSuccess) e = launch_residual(x->f, dt, thf, fef, fif, nullptr, x->res, x->B, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r.data(), x->res, r.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      st = PFSH_EHIP;
+      break;
+    }
+    if (iterations) *iterations = k + 1;
+    if (residuals) std::copy(r.begin(), r.end(), residuals + (size_t)k * r.size());
+    bool done = true, finite = true;
+    for (size_t i = 0; i < r.size(); ++i) {
+      if (!std::isfinite(r[i])) finite = false;
+      if (!(r[i] <= tol[i % 3])) done = false;
+    }
+    if (!finite) {
+      st = PFSH_ENONFINITE;
+      break;
+    }
+    if (done || k == max_iter - 1) break;
+    if (iterate_bd(x, dt, thf, fef, fif, s) != hipSuccess) {
+      st = PFSH_EHIP;
+      break;
+    }
+  }
+  (void)hipSetDevice(prev);
+  return st;
+}
+
+extern "C" pfsh_status pfsh_sdc_run(pfsh_level* lv, double dt, void* theta, void* f_expl,
+                                    void* f_impl, int nsteps, int nsweeps, int batch, void* stream) {
+  if (!lv || !theta || !f_expl || !f_impl) return PFSH_EINVAL;
+  if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0 || nsweeps < 1) return PFSH_EINVAL;
+  if (batch < 1 || batch > lv->d.max_batch) return PFSH_ESHAPE;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(lv->device);
+  hipStream_t s = (hipStream_t)stream;
+  double* th = (double*)theta;
+  double* fe = (double*)f_expl;
+  double* fi = (double*)f_impl;
+  hipError_t e = hipSuccess;
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    e = start_step(lv, th, fe, fi, batch, s);
+    for (int k = 0; k < nsweeps && e == hipSuccess; ++k)
+      e = sweep_impl(lv, dt, th, fe, fi, nullptr, batch, s);
+    if (e == hipSuccess) e = next_step(lv, th, batch, s);
+  }
+  (void)hipSetDevice(prev);
+  return e == hipSuccess ? PFSH_OK : PFSH_EHIP;
+}
+
+extern "C" pfsh_status pfsh_mlsdc_run(pfsh_pfasst* x, double dt, void* theta_f, void* fe_f,
+                                      void* fi_f, int nsteps, int n_iter, void* stream) {
+  if (!x || !theta_f || !fe_f || !fi_f) return PFSH_EINVAL;
+  if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0 || n_iter < 1) return PFSH_EINVAL;
+  if (x->n_ts != 1) return PFSH_ESHAPE;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(x->f->device);
+  hipStream_t s = (hipStream_t)stream;
+  double* th = (double*)theta_f;
+  double* fe = (double*)fe_f;
+  double* fi = (double*)fi_f;
+  hipError_t e = hipSuccess;
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    e = start_step(x->f, th, fe, fi, x->B, s);
+    for (int k = 0; k < n_iter && e == hipSuccess; ++k) {
+      e = sweep_impl(x->f, dt, th, fe, fi, nullptr, x->B, s);
+      if (e == hipSuccess) e = iterate_bd(x, dt, th, fe, fi, s);
+    }
+    if (e == hipSuccess) e = next_step(x->f, th, x->B, s);
+  }
+  (void)hipSetDevice(prev);
+  return e == hipSuccess ? PFSH_OK : PFSH_EHIP;
 }

@@ -68,6 +68,9 @@ _SIGS = {
     "pfsh_pfasst_predict": ([_P, _D, _P, _P, _P, _P, _P], _I),
     "pfsh_pfasst_iterate": ([_P, _D, _P, _P, _P, _I, _P], _I),
     "pfsh_pfasst_run": ([_P, _D, _P, _P, _P, _I, _P, _I, _P], _I),
+    "pfsh_pfasst_run_tol": ([_P, _D, _P, _P, _P, _I, _P, ctypes.POINTER(_I), _P, _P], _I),
+    "pfsh_sdc_run": ([_P, _D, _P, _P, _P, _I, _I, _I, _P], _I),
+    "pfsh_mlsdc_run": ([_P, _D, _P, _P, _P, _I, _I, _P], _I),
     "pfsh_pfasst_set_levels": ([_P, _P, _P], _I),
     "pfsh_pfasst_set_graphs": ([_P, _I], _I),
 }
@@ -308,6 +311,15 @@ class Level:
                                    _ptr(tau), _ptr(out), B, _stream(theta)), "pfsh_residual")
         return out
 
+    def sdc_run(self, dt, theta, f_expl, f_impl, nsteps, nsweeps):
+        """Serial SDC(M+1, nsweeps) over nsteps steps; node 0 of theta holds
+        the initial states on entry, the final ones on return."""
+        B = theta.shape[0]
+        for t, n in ((theta, "theta"), (f_expl, "f_expl"), (f_impl, "f_impl")):
+            self._st(t, n)
+        _check(lib().pfsh_sdc_run(self._h, float(dt), _ptr(theta), _ptr(f_expl), _ptr(f_impl),
+                                  int(nsteps), int(nsweeps), B, _stream(theta)), "pfsh_sdc_run")
+
     def residual_noalloc(self, dt, theta, f_expl, f_impl, tau=None, out=None):
         """pfsh_residual_noalloc: the residual with its partial maxima in the
         library's static device scratch (no allocation; `out` must be given
@@ -436,3 +448,28 @@ class Pfasst:
         _check(lib().pfsh_pfasst_iterate(self._h, float(dt), _ptr(theta_f), _ptr(fe_f),
                                          _ptr(fi_f), int(bool(last)), _stream(theta_f)),
                "pfsh_pfasst_iterate")
+
+    def mlsdc_run(self, dt, theta_f, fe_f, fi_f, nsteps, n_iter):
+        """MLSDC(Mf+1, Mc+1, n_iter) over nsteps steps (a context with n_ts = 1);
+        node 0 of theta_f holds the initial states on entry, the final ones on
+        return."""
+        for t, n in ((theta_f, "theta_f"), (fe_f, "fe_f"), (fi_f, "fi_f")):
+            self._fine(t, n)
+        _check(lib().pfsh_mlsdc_run(self._h, float(dt), _ptr(theta_f), _ptr(fe_f), _ptr(fi_f),
+                                    int(nsteps), int(n_iter), _stream(theta_f)), "pfsh_mlsdc_run")
+
+    def run_tol(self, dt, theta_f, fe_f, fi_f, max_iter, tol):
+        """Iterations until every slice's fine residual is at most tol (three
+        per-variable bounds) after a fine sweep, or max_iter; returns (the
+        number of iterations, residuals [iterations][B][3] as numpy)."""
+        import numpy as np
+        for t, n in ((theta_f, "theta_f"), (fe_f, "fe_f"), (fi_f, "fi_f")):
+            self._fine(t, n)
+        tl = (ctypes.c_double * 3)(*[float(v) for v in tol])
+        res = np.zeros((int(max_iter), self.B, 3))
+        it = ctypes.c_int()
+        code = lib().pfsh_pfasst_run_tol(self._h, float(dt), _ptr(theta_f), _ptr(fe_f), _ptr(fi_f),
+                                         int(max_iter), ctypes.cast(tl, ctypes.c_void_p), ctypes.byref(it),
+                                         res.ctypes.data_as(ctypes.c_void_p), _stream(theta_f))
+        _check(code, "pfsh_pfasst_run_tol")
+        return it.value, res[: it.value]
