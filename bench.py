@@ -428,6 +428,62 @@ def serial_reference(torch, pfsh, inputs, nsweeps=20):
     return np.concatenate(out)       # [step * members + member]
 
 
+def comparators(torch, pfsh, inputs, costmodel, block_ms_fp64, x_pfasst_fp64, xref, n_pf):
+    """The serial schemes of Sec. 5.5 on the same kernels and time steps as the
+    block (FP64): SDC(5, N_S = 8) and MLSDC(5, 3, N_ML = 4, 1/2) over the 16
+    steps of dt, timed with HIP events (one run after a warm-up), their end
+    states against serial collocation, and the speedups of the FP64 PFASST
+    block over them next to the cost model's (which counts operator
+    applications, not the batching of the slices on one GPU)."""
+    Tf, nlf, nof, nnf = FINE
+    Tc, nlc, noc, nnc = COARSE
+    x0 = torch.from_numpy(initial_states(inputs)).to("cuda")
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=MEMBERS)
+    th, fe, fi = gl.space_time(MEMBERS), gl.space_time(MEMBERS), gl.space_time(MEMBERS)
+    ns = 8
+
+    def run_sdc():
+        th[:, 0] = x0
+        gl.sdc_run(DT, th, fe, fi, N_TS, ns)
+    ms = timed(run_sdc)
+    end = th[:, 0].cpu().numpy()
+    out["sdc"] = {"scheme": f"SDC({nnf},{ns})", "ms": ms, "steps": N_TS,
+                  "rel_err_vs_collocation_last_step": rel_err_slices(end, xref[-MEMBERS:])}
+    gc = pfsh.Level(Tc, nlc, noc, nnc, max_batch=MEMBERS * nnc)
+    pf = pfsh.Pfasst(gl, gc, 1, MEMBERS)
+    nml = 4
+
+    def run_ml():
+        th[:, 0] = x0
+        pf.mlsdc_run(DT, th, fe, fi, N_TS, nml)
+    ms = timed(run_ml)
+    end = th[:, 0].cpu().numpy()
+    out["mlsdc"] = {"scheme": f"MLSDC({nnf},{nnc},{nml},1/2)", "ms": ms, "steps": N_TS,
+                    "rel_err_vs_collocation_last_step": rel_err_slices(end, xref[-MEMBERS:])}
+    pf.close()
+    alpha = (Tc + 1) / (Tf + 1)
+    out["pfasst_fp64"] = {"scheme": f"PFASST({N_TS},{nnf},{nnc},{n_pf},1/2)", "ms": block_ms_fp64,
+                          "rel_err_vs_collocation_last_step":
+                              rel_err_slices(x_pfasst_fp64[-MEMBERS:], xref[-MEMBERS:])}
+    out["speedup_vs_sdc"] = {"gpu": out["sdc"]["ms"] / block_ms_fp64,
+                             "cost_model": costmodel.speedup_vs_sdc(N_TS, nnf - 1, nnc - 1, n_pf, alpha, ns)}
+    out["speedup_vs_mlsdc"] = {"gpu": out["mlsdc"]["ms"] / block_ms_fp64,
+                               "cost_model": costmodel.speedup_vs_mlsdc(N_TS, nnf - 1, nnc - 1, n_pf, alpha, nml)}
+    return out
+
+
 def sweep_benchmark(torch, pfsh, inputs, reps=20, rounds=5):
     """The batched fine sweep alone, per transform precision: 16 independent
     seeded states (seeds 300..315, spread initial guess) at the fine level,
@@ -618,6 +674,8 @@ def main():
     err_iter_pure = [rel_err_slices(a, b) for a, b in zip(spure, s64)]
     xref = serial_reference(torch, pfsh, inputs)
     sweeps = sweep_benchmark(torch, pfsh, inputs)
+    from paper_1904_05988_amd import costmodel
+    comps = comparators(torch, pfsh, inputs, costmodel, r64["ms"], x64, xref, args.n_pf)
 
     # the kernel with the largest time per block over all levels and batches,
     # and every (level, kernel, batch) group against its own bound
@@ -683,6 +741,7 @@ def main():
             "mixed_without_fp64_iterations": rel_err_slices(xpure, xref)},
         "sweep_only_ms": rmx["sweep_ms"],
         "sweep_benchmark": sweeps,
+        "comparators": comps,
         "sht_tflops": sht / (rmx["ms"] * 1e-3) / 1e12,
         "kernel_ms_per_step_all_levels": rpr["per_level"],
         "tuned_variants": rmx["tuned"],
