@@ -10,8 +10,8 @@ chain, interpolation of the increments, new initial conditions; the last
 iteration stops after its fine sweep), then the fine collocation residual.
 "sweeps/s" counts batched fine sweeps (all 16 slices) per second.
 
-The headline block runs the transform stages in mixed precision (FP32 by
-default) and its last two iterations with FP64 fine levels; the same block in
+The headline block runs the transform stages of both levels in mixed
+precision (FP32 by default) and its last two iterations with FP64 levels; the same block in
 plain FP64 is timed next to it, and the states of the two are compared after
 every iteration (and against serial FP64 SDC on the same time steps, the
 collocation solution PFASST converges to).
@@ -281,8 +281,8 @@ def sht_roundtrip_benchmark(torch, pfsh, reps=20, rounds=5):
 
 def make_block(args, mixed, n64, pfsh, inputs, torch):
     """Levels, PFASST context, arrays and the block closure for one precision
-    recipe: fine transforms in `mixed` (FP64 for its last n64 iterations),
-    coarse level in FP64 (its serial chain is latency-bound, not arithmetic-bound)."""
+    recipe: the transforms of both levels in `mixed`, FP64 levels for the last
+    n64 iterations (--coarse-fp64: the coarse level FP64 throughout)."""
     dev = torch.device("cuda", 0)
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
@@ -290,8 +290,11 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
     # workspaces for all nodes of all slices at once (F at every node in one call)
     gfm = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B * nnf, precision=mixed)
     gc = pfsh.Level(Tc, nlc, noc, nnc, max_batch=B * nnc)
+    # coarse level of the mixed iterations: FP64, or the fine level's precision
+    gcm = gc if (mixed == "fp64" or getattr(args, "coarse_fp64", False)) else \
+        pfsh.Level(Tc, nlc, noc, nnc, max_batch=B * nnc, precision=mixed)
     gf64 = gfm if (mixed == "fp64" or n64 == 0) else pfsh.Level(Tf, nlf, nof, nnf, max_batch=B)
-    pf = pfsh.Pfasst(gfm, gc, N_TS, MEMBERS)
+    pf = pfsh.Pfasst(gfm, gcm, N_TS, MEMBERS)
     th0 = torch.from_numpy(initial_states(inputs)).to(dev)
     thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
     res = torch.empty((B, 3), dtype=torch.float64, device=dev)
@@ -307,15 +310,15 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
         # kernels of a sweep evict the tables between two launches of a stage.
         # The coarse chain runs its stages back to back (hot caches).
         for name, lv, batches in (("fine", gfm, fine_b + [B * nnf]), ("fine_fp64", gf64, fine_b),
-                                  ("coarse", gc, coarse_b)):
-            if name == "fine_fp64" and gf64 is gfm:
+                                  ("coarse", gc, coarse_b), ("coarse_mixed", gcm, coarse_b)):
+            if (name == "fine_fp64" and gf64 is gfm) or (name == "coarse_mixed" and gcm is gc):
                 continue
             tuned[name] = {b: {k: v[0] for k, v in lv.autotune(b, reps=10, cold=name != "coarse").items()}
                            for b in batches}
         torch.cuda.synchronize()
 
     def block():
-        pf.set_levels(gfm, gc)
+        pf.set_levels(gfm, gcm)
         pf.predict(DT, th0, thf, fef, fif)
         if args.schedule == "wavefront":
             pf.run(DT, thf, fef, fif, args.n_pf, fine_alt=None if n64 == 0 else gf64,
@@ -327,7 +330,7 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
                 pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
         gf64.residual(DT, thf, fef, fif, out=res)
 
-    return dict(block=block, pf=pf, levels=(gfm, gc, gf64), arrays=(thf, fef, fif), res=res,
+    return dict(block=block, pf=pf, levels=(gfm, gc, gf64, gcm), arrays=(thf, fef, fif), res=res,
                 tuned=tuned)
 
 
@@ -335,8 +338,9 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
     """K timed PFASST blocks of one precision recipe."""
     ctx = make_block(args, mixed, n64, pfsh, inputs, torch)
     pf, block = ctx["pf"], ctx["block"]
-    gfm, gc, gf64 = ctx["levels"]
-    named = [("fine", gfm), ("coarse", gc)] + ([] if gf64 is gfm else [("fine_fp64", gf64)])
+    gfm, gc, gf64, gcm = ctx["levels"]
+    named = ([("fine", gfm), ("coarse", gc)] + ([] if gf64 is gfm else [("fine_fp64", gf64)])
+             + ([] if gcm is gc else [("coarse_mixed", gcm)]))
     thf, fef, fif = ctx["arrays"]
     stream = torch.cuda.Stream()
     pf.set_graphs(not profile)
@@ -392,10 +396,10 @@ def run_states(args, mixed, n64, torch, pfsh, inputs):
     a.schedule = "iterations"
     a.no_tune = True
     ctx = make_block(a, mixed, n64, pfsh, inputs, torch)
-    pf, (gfm, gc, gf64) = ctx["pf"], ctx["levels"]
+    pf, (gfm, gc, gf64, gcm) = ctx["pf"], ctx["levels"]
     thf, fef, fif = ctx["arrays"]
     th0 = torch.from_numpy(initial_states(inputs)).to("cuda")
-    pf.set_levels(gfm, gc)
+    pf.set_levels(gfm, gcm)
     pf.predict(DT, th0, thf, fef, fif)
     out = []
     for k in range(args.n_pf):
@@ -629,6 +633,10 @@ def main():
     ap.add_argument("--schedule", default="iterations", choices=["wavefront", "iterations"],
                     help="order of the PFASST work inside a block (same arithmetic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--coarse-fp64", action="store_true",
+                    help="keep the coarse level in FP64 during the mixed iterations too (by "
+                         "default its transforms take the mixed precision until the first FP64 "
+                         "iteration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default transform-kernel variants (no autotuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -682,7 +690,8 @@ def main():
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
     B = N_TS * MEMBERS
-    geom = {"fine": (FINE, args.mixed), "fine_fp64": (FINE, "fp64"), "coarse": (COARSE, "fp64")}
+    geom = {"fine": (FINE, args.mixed), "fine_fp64": (FINE, "fp64"), "coarse": (COARSE, "fp64"),
+            "coarse_mixed": (COARSE, args.mixed)}
     groups = []
     for g in rpr["per_level"].pop("_groups"):
         (T, nlat, nlon, nn), prec = geom[g["level"]]
@@ -722,7 +731,8 @@ def main():
                    "coarse": f"T{Tc} {nlc}x{noc} {nnc} nodes", "slices": N_TS,
                    "members": MEMBERS, "spectrum": f"n^-{POWER:g}", "dt_s": DT,
                    "n_pf": args.n_pf, "fp64_final_iterations": args.n64,
-                   "schedule": args.schedule, "coarse_precision": "fp64",
+                   "schedule": args.schedule,
+                   "coarse_precision": "fp64" if args.coarse_fp64 else f"{args.mixed} then fp64",
                    "step": "one PFASST block: predictor + n_pf iterations, fine residual",
                    "seeds": list(SEEDS), "parallelism": "slices x members as batch, 1 GPU"},
         "roofline": roof,

@@ -226,9 +226,7 @@ typedef enum {
   PFSH_K_SWEEP_NODE = 5,  /* sweep node: F_E assembly of the previous node,
                              old-iterate terms (node 1), update, implicit
                              solve, F_I, transform input of the new state  */
-  PFSH_K_SWEEP_PRE = 6,   /* not launched: the old-iterate terms run in the
-                             first node kernel (kept for numbering)        */
-  PFSH_K_COUNT = 7
+  PFSH_K_COUNT = 6
 } pfsh_kernel_id;
 pfsh_status pfsh_profile_enable(pfsh_level* level, int on);
 pfsh_status pfsh_profile_read(pfsh_level* level, int kernel, int* launches, double* total_ms);

@@ -306,7 +306,8 @@ struct SrcPtrs {
   double* fe_pending;
 };
 
-// One node of the IMEX sweep in Q form (Sec. 4, eq. update), node = 1..M, for
+// One node of the IMEX sweep in Q form (Sec. 5.1.1, eq.
+// update_equation_sdcq_discrete_form), node = 1..M, for
 // one mode k = (m, n) of slice b of [batch][nn][3][K] arrays:
 //  node == 1: (optionally first taking node 0 -- state, F_E, F_I -- from src
 //      and storing it) S_i = Theta^0 + dt sum_j Q_ij (F_E^j + F_I^j)
