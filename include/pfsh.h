@@ -59,6 +59,22 @@ typedef enum {
                       MFMA with FP32 accumulate; FFT and products in FP32     */
 } pfsh_precision;
 
+/* Flag OR-ed into pfsh_level_desc.precision (FP64 and FP32 only): the level
+ * stores no Legendre tables.  The Legendre contractions generate the
+ * normalized P_n^m(mu_j) they need inside the kernel, in FP64, by the
+ * three-term recurrence in n (Sec. 3; the on-the-fly evaluation of the
+ * transform the paper builds on) taken two degrees at a time so that each
+ * parity runs on its own:
+ *   P_{n+2} = ((mu^2 - e_{n+1}^2 - e_n^2) P_n - e_n e_{n-1} P_{n-2}) / (e_{n+1} e_{n+2}),
+ *   e_n = sqrt((n^2 - m^2) / (4 n^2 - 1)),
+ * restarted every 32 degrees of one parity from two stored values (about 1/8
+ * of the FP32 table's size), and round the values to the transform type for
+ * the MFMA operands.  Results agree with the tabulated mode to the rounding
+ * of the recurrence (about 1e-14 relative in FP64).  The batch-1/2 fused node
+ * kernel needs the tables, so such a level runs small batches on the separate
+ * kernels.  Invalid (PFSH_EINVAL) with PFSH_BF16X3. */
+#define PFSH_LEGENDRE_RECURRENCE 0x100
+
 /* One space-time level of the hierarchy (Sec. 5.3). */
 typedef struct {
   int T;          /* triangular truncation (largest wavenumber), 1 <= T <= 767         */
@@ -70,7 +86,7 @@ typedef struct {
   double omega;   /* rotation rate Omega [1/s]; Coriolis f = 2 Omega mu               */
   double phibar;  /* mean geopotential Phibar [m^2/s^2]                                */
   double nu;      /* diffusion coefficient nu [m^2/s]                                  */
-  int precision;  /* pfsh_precision of the transform stages                            */
+  int precision;  /* pfsh_precision of the transform stages, | PFSH_LEGENDRE_RECURRENCE */
 } pfsh_level_desc;
 
 typedef struct pfsh_level pfsh_level;
@@ -85,7 +101,9 @@ pfsh_status pfsh_level_desc_check(const pfsh_level_desc* desc);
 
 /* Create a level on `device`: Gaussian grid, normalized Legendre tables up to
  * degree T+1 (built in 80-bit extended precision on the host, then rounded and
- * packed in the MFMA operand order of the chosen precision), FFT twiddles, the
+ * packed in the MFMA operand order of the chosen precision; with
+ * PFSH_LEGENDRE_RECURRENCE the recurrence's restart values and coefficients
+ * instead), FFT twiddles, the
  * SDC matrices Q, qE, qI of Sec. 5.1.1 and a workspace for max_batch.
  * *out receives the handle (NULL on failure).  Synchronous. */
 pfsh_status pfsh_level_create(const pfsh_level_desc* desc, int device, pfsh_level** out);
@@ -100,6 +118,13 @@ void pfsh_level_destroy(pfsh_level* level);
  * mu[nlat] and w[nlat]: Gaussian latitudes (north to south) and weights. */
 pfsh_status pfsh_level_query(const pfsh_level* level, int* K, int* n_nodes, double* nodes,
                              double* q, double* qe, double* qi, double* mu, double* w);
+
+/* Device memory of a level in bytes (either pointer may be NULL): *tables =
+ * the Legendre tables, or in recurrence mode the restart pairs and
+ * coefficients that replace them; *workspace = the transform and sweep
+ * workspace sized for max_batch.  Host-only. */
+pfsh_status pfsh_level_bytes(const pfsh_level* level, unsigned long long* tables,
+                             unsigned long long* workspace);
 
 /* Scalar SH synthesis (Sec. 3, eq. spectral_to_physical_space):
  * spec [nfields][K] complex128 -> grid [nfields][nlat][nlon] float64,

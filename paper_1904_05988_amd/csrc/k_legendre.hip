@@ -398,6 +398,289 @@ __global__ __launch_bounds__(128) void k_leg_anal_tall(const void* __restrict__ 
     }
 }
 
+// ------------------------------------------------------------ recurrence mode
+// Levels created with PFSH_LEGENDRE_RECURRENCE hold no tables: each workgroup
+// evaluates the P_n^m(mu_j) its contraction needs, in FP64, by the two-degree
+// recurrence P_{n+2} = a ((mu^2 - b) P_n - c P_{n-2}) restarted every
+// kRecChunk degrees of one parity from a stored pair, rounds them to the
+// transform type and keeps them in LDS in MFMA operand order; the data operand
+// and the outputs are those of the tabulated kernels.
+
+// Makes a wave's LDS writes visible to its own later LDS reads (the LDS
+// serves one wave's accesses in order; the fences keep the compiler from
+// moving accesses across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One recurrence chunk of one ring: the pair (P_{n0-2}, P_{n0}) from `sd`,
+// then kRecChunk values P_{n0}, P_{n0+2}, ... (value t uses the coefficients
+// cf[3 (t0 + t)]), each handed to put(t, value); degrees at or past np are 0.
+template <typename Put>
+__device__ __forceinline__ void rec_chunk(const double* __restrict__ sd, bool live, double x2,
+                                          const double* cf, int t0, int i0, int np, Put put) {
+  double s0 = 0.0, s1 = 0.0;
+  if (live) {
+    s0 = sd[0];
+    s1 = sd[1];
+  }
+  put(0, i0 < np ? s1 : 0.0);
+#pragma unroll 4
+  for (int t = 1; t < kRecChunk; ++t) {
+    const double* c3 = cf + 3 * (t0 + t);
+    const double s2 = c3[0] * ((x2 - c3[1]) * s1 - c3[2] * s0);
+    s0 = s1;
+    s1 = s2;
+    put(t, i0 + t < np ? s1 : 0.0);
+  }
+}
+
+// Synthesis, the items and tiles of k_leg_synth (MC orders of one parity, wave
+// w takes order m0 + w, 32 rings x 32 columns).  Each wave walks its order's
+// degrees from the highest down in slabs of 2 kRecChunk: it loads the slab's
+// data-operand fragments, stages the slab's recurrence coefficients, lets lane
+// (ring r, chunk h) generate 32 degrees of ring r into its private LDS slab and
+// runs the slab's k-blocks, highest first (FP32: two chains by k-block
+// parity).  The results go out through the LDS exchange of k_leg_synth.
+template <class Op, int MC>
+__global__ __launch_bounds__(64 * MC) void k_leg_synth_rec(
+    const double* __restrict__ seeds, const double* __restrict__ rec, const double* __restrict__ mu,
+    const void* __restrict__ X, typename Op::R* __restrict__ F4, const MPInfo* __restrict__ mpi,
+    const WorkItem* __restrict__ items, int nitems, int ntile, int nct, int CBs, int CBn,
+    int ncols, int nf, int J, int Jp, int T, int Lp) {
+  typedef typename Op::R R;
+  typedef typename Op::C C;
+  constexpr int SM = MC + 1;
+  constexpr int SLAB = 2 * kRecChunk, KPS = SLAB / 4;   // degrees and k-blocks per slab
+  constexpr bool SPL = SplitAcc<Op>::value;
+  extern __shared__ unsigned char smem_raw[];
+  R* slabs = reinterpret_cast<R*>(smem_raw);                                  // [MC][KPS][2][64]
+  double* coef = reinterpret_cast<double*>(smem_raw + (size_t)MC * KPS * 128 * sizeof(R));  // [MC][SLAB][3]
+  R* stage = slabs;   // the output exchange reuses the slabs once every wave is done
+  int item;
+  int sub;
+  if (!xcd_group(nitems, ntile * nct, item, sub)) return;
+  const int tile = sub / nct, ct = sub - tile * nct;
+  const WorkItem it = items[item];
+  const int p = it.mp & 1, m0 = it.mp >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb0 = tile * 2, cb0 = ct * 2;
+  const bool c1 = cb0 + 1 < CBn;
+  const int m = m0 + wave;
+  C acc[4] = {}, odd[4] = {};
+  if (m <= T) {
+    const MPInfo q = mpi[2 * m + p];
+    R* slab = slabs + (size_t)wave * KPS * 128;
+    double* cf = coef + (size_t)wave * SLAB * 3;
+    const int r = lane & 31, h = lane >> 5, j = rb0 * 16 + r;
+    const double x = j < J ? mu[j] : 0.0, x2 = x * x;
+    const int nch = rec_chunks(q.np);
+    const int ebase = ext_off(T, m) + p;
+    for (int s = (q.np + SLAB - 1) / SLAB - 1; s >= 0; --s) {
+      const int kb_lo = s * KPS, kb_hi = min(q.kbS, kb_lo + KPS);
+      typename Op::A b0[KPS], b1[KPS];
+#pragma unroll
+      for (int kl = 0; kl < KPS; ++kl) {
+        const long long kb = kb_lo + kl < kb_hi ? kb_lo + kl : kb_hi - 1;
+        b0[kl] = Op::load(X, q.xS + cb0 + kb * CBs, lane);
+        b1[kl] = c1 ? Op::load(X, q.xS + cb0 + 1 + kb * CBs, lane) : b0[kl];
+      }
+      wave_lds_sync();   // this wave's reads of the previous slab are done
+      {
+        const int i = s * SLAB + lane;    // degree index whose coefficients lane stages
+        double a = 0.0, b = 0.0, c = 0.0;
+        if (i >= 1 && i < q.np) {
+          const double* rc = rec + (size_t)(ebase + 2 * (i - 1)) * 4;
+          a = rc[0];
+          b = rc[1];
+          c = rc[2];
+        }
+        cf[3 * lane] = a;
+        cf[3 * lane + 1] = b;
+        cf[3 * lane + 2] = c;
+      }
+      wave_lds_sync();
+      const int ch = 2 * s + h;
+      rec_chunk(seeds + ((size_t)(q.seed + ch) * Jp + j) * 2, ch < nch && j < J, x2, cf,
+                h * kRecChunk, ch * kRecChunk, q.np, [&](int t, double v) {
+                  const int dl = h * kRecChunk + t;
+                  slab[((dl >> 2) * 2 + (r >> 4)) * 64 + (dl & 3) * 16 + (r & 15)] = (R)v;
+                });
+      wave_lds_sync();
+#pragma unroll
+      for (int kl = KPS - 1; kl >= 0; --kl) {
+        if (kb_lo + kl >= kb_hi) continue;   // uniform
+        const typename Op::A a0 = slab[(kl * 2) * 64 + lane], a1 = slab[(kl * 2 + 1) * 64 + lane];
+        auto blocks = [&](C (&d)[4]) {
+          d[0] = Op::mma(a0, b0[kl], d[0]);
+          if (c1) d[1] = Op::mma(a0, b1[kl], d[1]);
+          d[2] = Op::mma(a1, b0[kl], d[2]);
+          if (c1) d[3] = Op::mma(a1, b1[kl], d[3]);
+        };
+        if (SPL && (kl & 1))
+          blocks(odd);
+        else
+          blocks(acc);
+      }
+    }
+  }
+  if constexpr (SPL) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] += odd[b];
+  }
+  __syncthreads();   // every wave is done with its slab before the exchange reuses it
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int rr = (blk >> 1) * 16, cc = (blk & 1) * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] = (R)acc[blk][v];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 32 * 16; t += 64 * MC) {
+    const int rw = t >> 4, cp = t & 15;
+    const int j = rb0 * 16 + rw, c = cb0 * 16 + 2 * cp;
+    if (j >= J || c >= ncols) continue;
+    const int bf = c >> 1, f = bf % nf, b = bf / nf;
+    R out[2 * MC];
+    const R* re = stage + (rw * 32 + 2 * cp) * SM;
+    const R* im = re + SM;
+#pragma unroll
+    for (int mi = 0; mi < MC; ++mi) {
+      out[2 * mi] = re[mi];
+      out[2 * mi + 1] = im[mi];
+    }
+    store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
+  }
+}
+
+// Analysis, the items and column tiles of k_leg_anal shape 0 (one (m, p) and
+// 64 degrees = two recurrence chunks per workgroup, 4 waves of 2 x 2 blocks).
+// The rings are taken in slabs of SR (64 degrees x SR rings fill 64 KiB): the
+// workgroup generates the slab's operand (thread task = (ring, chunk)), then
+// every wave runs its blocks over the slab's k-blocks with the data operand
+// PF k-blocks ahead (FP32: two chains by k-block parity).  A k-block row of
+// the LDS tile is padded by one element so that the generating threads, which
+// run over rings, spread over the banks.
+template <class Op, int PF, bool C1>
+__device__ __forceinline__ void anal_rec_slab(const typename Op::R* As, int KS, int rbl,
+                                              const void* __restrict__ G, long long tb,
+                                              long long bstep, int nk, int lane,
+                                              typename Op::C (&acc)[4], typename Op::C (&odd)[4]) {
+  constexpr bool SPL = SplitAcc<Op>::value;
+  static_assert(!SPL || PF % 2 == 0, "two chains need an even prefetch depth");
+  typename Op::A b0[PF], b1[PF];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) {
+    const long long k = s < nk ? s : nk - 1;
+    b0[s] = Op::load(G, tb + k * bstep, lane);
+    if (C1) b1[s] = Op::load(G, tb + k * bstep + 1, lane);
+  }
+  for (int k0 = 0; k0 < nk; k0 += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      const int kl = k0 + s;
+      if (kl < nk) {
+        const typename Op::A a0 = As[kl * KS + rbl * 64 + lane];
+        const typename Op::A a1 = As[kl * KS + (rbl + 1) * 64 + lane];
+        auto blocks = [&](typename Op::C (&d)[4]) {
+          d[0] = Op::mma(a0, b0[s], d[0]);
+          if (C1) d[1] = Op::mma(a0, b1[s], d[1]);
+          d[2] = Op::mma(a1, b0[s], d[2]);
+          if (C1) d[3] = Op::mma(a1, b1[s], d[3]);
+        };
+        if (SPL && (s & 1))
+          blocks(odd);
+        else
+          blocks(acc);
+      }
+      const long long k = kl + PF < nk ? kl + PF : nk - 1;
+      b0[s] = Op::load(G, tb + k * bstep, lane);
+      if (C1) b1[s] = Op::load(G, tb + k * bstep + 1, lane);
+    }
+  }
+}
+
+template <class Op, int PF>
+__global__ __launch_bounds__(256) void k_leg_anal_rec(
+    const double* __restrict__ seeds, const double* __restrict__ rec, const double* __restrict__ mu,
+    const void* __restrict__ G, typename Op::R* __restrict__ Y, const MPInfo* __restrict__ mpi,
+    const WorkItem* __restrict__ items, int nitems, int nct, int kb2, int CBa, int CBn,
+    int ncols, int Kx, int J, int Jp, int T) {
+  typedef typename Op::R R;
+  typedef typename Op::C C;
+  constexpr int SR = 65536 / (64 * (int)sizeof(R));   // rings per slab
+  constexpr int KS = 4 * 64 + 1;                       // padded k-block row of the tile
+  extern __shared__ unsigned char smem_raw[];
+  R* As = reinterpret_cast<R*>(smem_raw);                                      // [SR/4][KS]
+  double* cf = reinterpret_cast<double*>(smem_raw + (size_t)(SR / 4) * KS * sizeof(R));  // [64][3]
+  int item, ct;
+  if (!xcd_tile(nitems, nct, item, ct)) return;
+  const WorkItem it = items[item];
+  const MPInfo q = mpi[it.mp];
+  if (it.tile * 4 >= q.rbA) return;                    // padding item (whole workgroup)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rbl = (wave >> 1) * 2, cb0 = ct * 4 + (wave & 1) * 2;
+  const bool live = cb0 < CBn, c1 = cb0 + 1 < CBn;
+  const int deg0 = it.tile * 64, nch = rec_chunks(q.np), ebase = ext_off(T, q.m) + q.p;
+  if (threadIdx.x < 64) {
+    const int i = deg0 + threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (i >= 1 && i < q.np) {
+      const double* rc = rec + (size_t)(ebase + 2 * (i - 1)) * 4;
+      a = rc[0];
+      b = rc[1];
+      c = rc[2];
+    }
+    cf[3 * threadIdx.x] = a;
+    cf[3 * threadIdx.x + 1] = b;
+    cf[3 * threadIdx.x + 2] = c;
+  }
+  C acc[4] = {}, odd[4] = {};
+  for (int j0 = 0; j0 < Jp; j0 += SR) {
+    const int sr = min(SR, Jp - j0);
+    __syncthreads();   // coefficients staged; the previous slab has been read
+    for (int task = threadIdx.x; task < 2 * sr; task += 256) {
+      const int jj = task % sr, hh = task / sr, j = j0 + jj, ch = 2 * it.tile + hh;
+      const double x = j < J ? mu[j] : 0.0;
+      R* dst = As + (jj >> 2) * KS + (jj & 3) * 16;
+      rec_chunk(seeds + ((size_t)(q.seed + ch) * Jp + j) * 2, ch < nch && j < J, x * x, cf,
+                hh * kRecChunk, ch * kRecChunk, q.np, [&](int t, double v) {
+                  const int dl = hh * kRecChunk + t;
+                  dst[(dl >> 4) * 64 + (dl & 15)] = (R)v;
+                });
+    }
+    __syncthreads();
+    if (live) {
+      const long long tb = ((long long)it.mp * kb2 + j0 / 4) * CBa + cb0;
+      if (c1)
+        anal_rec_slab<Op, PF, true>(As, KS, rbl, G, tb, (long long)CBa, sr / 4, lane, acc, odd);
+      else
+        anal_rec_slab<Op, PF, false>(As, KS, rbl, G, tb, (long long)CBa, sr / 4, lane, acc, odd);
+    }
+  }
+  if (!live) return;
+  if constexpr (SplitAcc<Op>::value) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] += odd[b];
+  }
+  const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
+  const int rb0 = it.tile * 4 + rbl;
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int rb = rb0 + (blk >> 1), cb = cb0 + (blk & 1);
+    if ((blk & 1) && !c1) continue;
+    const int c = cb * 16 + (lane & 15);
+    if (c >= ncols) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb * 16 + Op::row(lane, v);
+      if (i < q.np) Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (R)acc[blk][v];
+    }
+  }
+}
+
 static inline unsigned xcd_grid(int nitems, int nct) {
   return (unsigned)(((nitems + 7) / 8) * 8 * nct);
 }
@@ -440,6 +723,36 @@ static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class Op>
+static hipError_t synth_rec_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
+  typedef typename Op::R R;
+  constexpr int MC = Op::KIND == OP_F64 ? 4 : 8;
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2, ntile = (lv->RB + 1) / 2;
+  const size_t shm = (size_t)MC * (2 * kRecChunk / 4) * 128 * sizeof(R) +
+                     (size_t)MC * 2 * kRecChunk * 3 * sizeof(double);
+  (void)hipFuncSetAttribute((const void*)k_leg_synth_rec<Op, MC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_leg_synth_rec<Op, MC>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+                     dim3(64 * MC), shm, s, lv->seeds_d, lv->rec_d, lv->mu_d, lv->X,
+                     (R*)lv->F4, lv->mp_d, lv->itemsS, lv->nitemsS, ntile, nct, lv->CBs, CBn,
+                     ncols, nf, lv->J, lv->Jp, lv->T, lv->Lp);
+  return hipGetLastError();
+}
+
+template <class Op>
+static hipError_t anal_rec_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
+  typedef typename Op::R R;
+  const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
+  constexpr int SR = 65536 / (64 * (int)sizeof(R));
+  const size_t shm = (size_t)(SR / 4) * (4 * 64 + 1) * sizeof(R) + (size_t)64 * 3 * sizeof(double);
+  (void)hipFuncSetAttribute((const void*)k_leg_anal_rec<Op, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_leg_anal_rec<Op, 4>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), shm, s,
+                     lv->seeds_d, lv->rec_d, lv->mu_d, lv->G, (R*)lv->Y, lv->mp_d, lv->itemsA,
+                     lv->nitemsA, nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->J, lv->Jp, lv->T);
+  return hipGetLastError();
+}
+
 // Variant lists (index 0 = default):
 //   synthesis, prefetch depth of the K loop (t4: 4x4-block wave tiles):
 //     FP64 / FP32 4 2 8 t4-4 t4-2 4h (4h: LDS exchange in two row halves);
@@ -454,6 +767,9 @@ int leg_variant_count(int op, int stage) {
 }
 
 hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
+  if (lv->rec_mode)
+    return lv->op == OP_F64 ? synth_rec_impl<OpF64>(lv, ncols, nf, s)
+                            : synth_rec_impl<OpF32>(lv, ncols, nf, s);
   const int v = lv->variant[TS_SYNTH][tune_bucket((ncols + 15) / 16)];
   switch (lv->op) {
     case OP_F64:
@@ -499,6 +815,8 @@ static hipError_t anal_variant(const pfsh_level* lv, int v, int ncols, hipStream
 }
 
 hipError_t launch_leg_anal(const pfsh_level* lv, int ncols, int /*nf*/, hipStream_t s) {
+  if (lv->rec_mode)
+    return lv->op == OP_F64 ? anal_rec_impl<OpF64>(lv, ncols, s) : anal_rec_impl<OpF32>(lv, ncols, s);
   const int v = lv->variant[TS_ANAL][tune_bucket((ncols + 15) / 16)];
   switch (lv->op) {
     case OP_F64: return anal_variant<OpF64>(lv, v, ncols, s);

@@ -1122,6 +1122,7 @@ static hipError_t node_fused_impl(const pfsh_level* lv, int node, int asm_node, 
 
 bool node_fused_ok(const pfsh_level* lv, int batch) {
   if (batch < 1 || batch > 2 || (lv->op != OP_F64 && lv->op != OP_F32)) return false;
+  if (lv->rec_mode) return false;   // the fused node reads the tables
   const size_t rsz = lv->op == OP_F64 ? 8 : 4;
   const int kbmax = (npar(lv->T, 0, 0) + 3) / 4;
   const size_t shm = (size_t)2 * 3 * (lv->T + 1) * 16 + (size_t)20 * (lv->T + 2) * rsz +

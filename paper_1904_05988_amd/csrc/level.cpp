@@ -41,7 +41,9 @@ extern "C" pfsh_status pfsh_level_desc_check(const pfsh_level_desc* d) {
   if (!(d->radius > 0) || !std::isfinite(d->radius)) return PFSH_EINVAL;
   if (!std::isfinite(d->omega) || !std::isfinite(d->phibar) || !(d->phibar >= 0)) return PFSH_EINVAL;
   if (!(d->nu >= 0) || !std::isfinite(d->nu)) return PFSH_EINVAL;
-  if (d->precision < PFSH_FP64 || d->precision > PFSH_BF16X3) return PFSH_EINVAL;
+  const int prec = d->precision & ~PFSH_LEGENDRE_RECURRENCE;
+  if (prec < PFSH_FP64 || prec > PFSH_BF16X3) return PFSH_EINVAL;
+  if ((d->precision & PFSH_LEGENDRE_RECURRENCE) && prec == PFSH_BF16X3) return PFSH_EINVAL;
   return PFSH_OK;
 }
 
@@ -51,7 +53,7 @@ static void free_level(pfsh_level* lv) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
-  void* ptrs[] = {lv->tabS, lv->tabA, lv->mp_d, lv->itemsS, lv->itemsA, lv->mu_d, lv->w_d,
+  void* ptrs[] = {lv->tabS, lv->tabA, lv->seeds_d, lv->rec_d, lv->mp_d, lv->itemsS, lv->itemsA, lv->mu_d, lv->w_d,
                   lv->tw_d, lv->eps_d, lv->X, lv->F4, lv->G, lv->Y, lv->S, lv->red};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -87,7 +89,9 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   if (!lv) return PFSH_ENOMEM;
   lv->d = *d;
   lv->device = device;
-  lv->op = d->precision == PFSH_FP64 ? OP_F64 : (d->precision == PFSH_FP32 ? OP_F32 : OP_BF16X3);
+  const int prec = d->precision & ~PFSH_LEGENDRE_RECURRENCE;
+  lv->op = prec == PFSH_FP64 ? OP_F64 : (prec == PFSH_FP32 ? OP_F32 : OP_BF16X3);
+  lv->rec_mode = (d->precision & PFSH_LEGENDRE_RECURRENCE) != 0;
   lv->T = d->T;
   lv->L = d->T + 1;
   lv->K = (d->T + 1) * (d->T + 2) / 2;
@@ -189,8 +193,11 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   sdc_matrices(lv->nn, lv->nodes, lv->Q, lv->QE, lv->QI);
 
   std::vector<unsigned char> tabS, tabA;
-  std::vector<double> unused;
-  build_tables(lv, tabS, tabA, unused);
+  std::vector<double> unused, seeds, rec;
+  if (lv->rec_mode)
+    build_recurrence(lv, seeds, rec);
+  else
+    build_tables(lv, tabS, tabA, unused);
 
   const size_t rsz = lv->op == OP_F64 ? 8 : 4;  // transform real type
   std::vector<unsigned char> tw(2 * rsz * lv->nlon);
@@ -220,8 +227,13 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
 
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-  chk(alloc_copy(&lv->tabS, tabS.data(), tabS.size()));
-  chk(alloc_copy(&lv->tabA, tabA.data(), tabA.size()));
+  if (lv->rec_mode) {
+    chk(alloc_copy(&lv->seeds_d, seeds.data(), seeds.size() * sizeof(double)));
+    chk(alloc_copy(&lv->rec_d, rec.data(), rec.size() * sizeof(double)));
+  } else {
+    chk(alloc_copy(&lv->tabS, tabS.data(), tabS.size()));
+    chk(alloc_copy(&lv->tabA, tabA.data(), tabA.size()));
+  }
   chk(alloc_copy(&lv->mp_d, lv->mp.data(), lv->mp.size() * sizeof(MPInfo)));
   chk(alloc_copy(&lv->itemsS, its.data(), its.size() * sizeof(WorkItem)));
   chk(alloc_copy(&lv->itemsA, ita.data(), ita.size() * sizeof(WorkItem)));
@@ -235,7 +247,7 @@ extern "C" pfsh_status pfsh_level_create(const pfsh_level_desc* d, int device, p
   chk(alloc_copy(&lv->S, nullptr, bytesS));
   chk(alloc_copy(&lv->red, nullptr, lv->red_len * sizeof(double)));
   chk(hipDeviceSynchronize());
-  lv->bytes_tables = tabS.size() + tabA.size();
+  lv->bytes_tables = tabS.size() + tabA.size() + (seeds.size() + rec.size()) * sizeof(double);
   lv->bytes_work = bytesX + bytesF4 + bytesG + bytesY + bytesS;
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
@@ -269,5 +281,13 @@ extern "C" pfsh_status pfsh_level_query(const pfsh_level* lv, int* K, int* n_nod
   if (qi) std::memcpy(qi, lv->QI, nn * nn * sizeof(double));
   if (mu) std::memcpy(mu, lv->mu_h.data(), lv->nlat * sizeof(double));
   if (w) std::memcpy(w, lv->w_h.data(), lv->nlat * sizeof(double));
+  return PFSH_OK;
+}
+
+extern "C" pfsh_status pfsh_level_bytes(const pfsh_level* lv, unsigned long long* tables,
+                                        unsigned long long* workspace) {
+  if (!lv) return PFSH_EINVAL;
+  if (tables) *tables = lv->bytes_tables;
+  if (workspace) *workspace = lv->bytes_work;
   return PFSH_OK;
 }

@@ -64,7 +64,16 @@ struct MPInfo {
   long long tabS;     // synthesis table: first block
   long long tabA;     // analysis table: first block
   long long xS;       // synthesis data operand: first block
+  long long seed;     // recurrence mode: first restart chunk of this (m, p)
 };
+
+// Recurrence mode (PFSH_LEGENDRE_RECURRENCE): the degrees i = 0..np-1 of one
+// (m, p) are cut into chunks of kRecChunk; chunk c restarts from the stored pair
+// (P_{n0-2}, P_{n0}), n0 = m + p + 2 kRecChunk c (P_{n0-2} = 0 below m), one
+// pair per padded ring j < Jp at seeds[(q.seed + c) Jp + j].  rec[ext_off(T, m)
+// + n - m] holds (a, b, c, 0) of P_{n+2} = a ((mu^2 - b) P_n - c P_{n-2}).
+constexpr int kRecChunk = 32;
+__host__ __device__ inline int rec_chunks(int np) { return (np + kRecChunk - 1) / kRecChunk; }
 
 struct WorkItem {      // one workgroup tile of a Legendre contraction
   int mp;              // (m, p) index; synthesis: first order of the m-chunk, 2 m0 + p
@@ -91,8 +100,6 @@ inline int tune_bucket(int n) {
   while (b < kTuneBuckets - 1 && (1 << b) < n) ++b;
   return b;
 }
-int variant_count(int op, int stage);
-
 }  // namespace pfsh
 
 struct pfsh_level {
@@ -111,6 +118,9 @@ struct pfsh_level {
   // device tables
   void* tabS = nullptr;    // packed synthesis table (A operand, rows = rings)
   void* tabA = nullptr;    // packed analysis table (A operand, rows = degrees)
+  bool rec_mode = false;   // PFSH_LEGENDRE_RECURRENCE: no tables, seeds + rec instead
+  double* seeds_d = nullptr;   // [chunks][Jp] (P_{n0-2}, P_{n0}) pairs
+  double* rec_d = nullptr;     // [Kx] (a, b, c, 0) of the two-degree recurrence
   pfsh::MPInfo* mp_d = nullptr;
   pfsh::WorkItem* itemsS = nullptr;  int nitemsS = 0;
   pfsh::WorkItem* itemsA = nullptr;  int nitemsA = 0;
@@ -165,6 +175,14 @@ void lagrange_matrix(int nsrc, const double* src, int ndst, const double* dst, d
 // Build packed tables for a level (host), returns bytes.
 void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<unsigned char>& tabA,
                   std::vector<double>& eps_ext);
+
+// Recurrence mode: restart pairs and coefficients (layouts at kRecChunk);
+// fills q.seed of every (m, p).  seeds: 2 doubles per (chunk, padded ring).
+void build_recurrence(pfsh_level* lv, std::vector<double>& seeds, std::vector<double>& rec);
+
+// Kernel variants of a stage on this level (1 for the Legendre stages and the
+// sweep path in recurrence mode).
+int variant_count(const pfsh_level* lv, int stage);
 
 // ------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.

@@ -231,4 +231,59 @@ void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<
   }
 }
 
+// Recurrence mode: instead of the packed tables, the values that restart the
+// two-degree recurrence every kRecChunk degrees of one parity, and its
+// coefficients.  With x P_k = e_{k+1} P_{k+1} + e_k P_{k-1} applied twice,
+//   e_{n+1} e_{n+2} P_{n+2} = (x^2 - e_{n+1}^2 - e_n^2) P_n - e_n e_{n-1} P_{n-2},
+// so a = 1 / (e_{n+1} e_{n+2}), b = e_{n+1}^2 + e_n^2, c = e_n e_{n-1} (e_k = 0
+// for k <= m).  The restart pairs come from the same 80-bit recurrence as the
+// tables, one ring at a time.
+void build_recurrence(pfsh_level* lv, std::vector<double>& seeds, std::vector<double>& rec) {
+  const int T = lv->T, J = lv->J, Jp = lv->Jp;
+  long long nch = 0;
+  for (auto& q : lv->mp) {
+    q.seed = nch;
+    nch += rec_chunks(q.np);
+  }
+  seeds.assign((size_t)nch * Jp * 2, 0.0);
+  rec.assign((size_t)lv->Kx * 4, 0.0);
+  // e_n^m of the extended layout (n = m..T+1)
+  std::vector<ld> ev((size_t)lv->Kx);
+  for (int m = 0; m <= T; ++m)
+    for (int n = m; n <= T + 1; ++n)
+      ev[ext_off(T, m) + n - m] = n > m ? std::sqrt((ld)(n * n - m * m) / (ld)(4 * n * n - 1)) : 0;
+  auto eps = [&](int n, int m) -> ld { return ev[ext_off(T, m) + n - m]; };
+  for (int m = 0; m <= T; ++m)
+    for (int n = m; n + 2 <= T + 1; ++n) {
+      const ld e0 = eps(n, m), e1 = eps(n + 1, m), e2 = eps(n + 2, m);
+      const ld em = n - 1 >= m ? eps(n - 1, m) : 0;
+      double* r = rec.data() + (size_t)(ext_off(T, m) + n - m) * 4;
+      r[0] = (double)(1 / (e1 * e2));
+      r[1] = (double)(e1 * e1 + e0 * e0);
+      r[2] = (double)(e0 * em);
+    }
+  std::vector<ld> row(T + 3);
+  for (int j = 0; j < J; ++j) {
+    const ld x = lv->mu_h[j];
+    const ld sn = std::sqrt((1 - x) * (1 + x));
+    ld pmm = 1 / std::sqrt((ld)2);
+    for (int m = 0; m <= T; ++m) {
+      if (m > 0) pmm = std::sqrt((ld)(2 * m + 1) / (ld)(2 * m)) * sn * pmm;
+      row[0] = pmm;
+      row[1] = std::sqrt((ld)(2 * m + 3)) * x * pmm;
+      for (int n = m + 2; n <= T + 1; ++n)
+        row[n - m] = (x * row[n - m - 1] - eps(n - 1, m) * row[n - m - 2]) / eps(n, m);
+      for (int p = 0; p < 2; ++p) {
+        const MPInfo& q = lv->mp[2 * m + p];
+        for (int c = 0; c < rec_chunks(q.np); ++c) {
+          const int d0 = p + 2 * kRecChunk * c;             // n0 - m
+          double* sd = seeds.data() + ((size_t)(q.seed + c) * Jp + j) * 2;
+          sd[0] = d0 >= 2 ? (double)row[d0 - 2] : 0.0;
+          sd[1] = (double)row[d0];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace pfsh

@@ -9,9 +9,11 @@ namespace pfsh {
 int leg_variant_count(int op, int stage);
 int ring_variant_count();
 
-int variant_count(int op, int stage) {
+int variant_count(const pfsh_level* lv, int stage) {
+  if (stage == TS_RING) return ring_variant_count();
+  if (lv->rec_mode) return 1;   // one recurrence kernel per Legendre stage, no fused node
   if (stage == TS_FUSE) return 2;
-  return stage == TS_RING ? ring_variant_count() : leg_variant_count(op, stage);
+  return leg_variant_count(lv->op, stage);
 }
 }  // namespace pfsh
 
@@ -48,13 +50,13 @@ struct DeviceGuard {
 
 extern "C" int pfsh_variant_count(const pfsh_level* lv, int stage) {
   if (!lv || stage < 0 || stage >= TS_COUNT) return PFSH_EINVAL;
-  return variant_count(lv->op, stage);
+  return variant_count(lv, stage);
 }
 
 extern "C" pfsh_status pfsh_level_set_variant(pfsh_level* lv, int stage, int batch, int variant) {
   if (!lv || stage < 0 || stage >= TS_COUNT) return PFSH_EINVAL;
   if (batch < 1 || batch > lv->d.max_batch) return PFSH_ESHAPE;
-  if (variant < 0 || variant >= variant_count(lv->op, stage)) return PFSH_EINVAL;
+  if (variant < 0 || variant >= variant_count(lv, stage)) return PFSH_EINVAL;
   lv->variant[stage][stage_bucket(stage, batch)] = (unsigned char)variant;
   return PFSH_OK;
 }
@@ -101,7 +103,7 @@ extern "C" pfsh_status pfsh_level_autotune_ex(pfsh_level* lv, int batch, int rep
   for (int stage = 0; stage < TS_TUNED && err == hipSuccess; ++stage) {
     unsigned char& slot = lv->variant[stage][stage_bucket(stage, batch)];
     const unsigned char keep = slot;
-    const int nv = variant_count(lv->op, stage);
+    const int nv = variant_count(lv, stage);
     float best_us[PFSH_MAX_VARIANTS];
     for (int v = 0; v < nv; ++v) best_us[v] = 3.0e38f;
     for (int r = 0; r < kRounds && err == hipSuccess; ++r) {

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfsh.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+LEGENDRE_RECURRENCE = 0x100   # flag OR-ed into LevelDesc.precision
 STATUS = {0: "PFSH_OK", -1: "PFSH_EINVAL", -2: "PFSH_ESHAPE", -3: "PFSH_ENOMEM",
           -4: "PFSH_EHIP", -5: "PFSH_EUNSUPPORTED", -6: "PFSH_ENONFINITE"}
 
@@ -42,6 +43,7 @@ _SIGS = {
     "pfsh_level_create": ([ctypes.POINTER(LevelDesc), _I, ctypes.POINTER(_P)], _I),
     "pfsh_level_destroy": ([_P], None),
     "pfsh_level_query": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P, _P, _P, _P, _P, _P], _I),
+    "pfsh_level_bytes": ([_P, ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong)], _I),
     "pfsh_sh_synthesis": ([_P, _P, _P, _I, _P], _I),
     "pfsh_sh_analysis": ([_P, _P, _P, _I, _P], _I),
     "pfsh_rhs": ([_P, _P, _P, _P, _I, _P], _I),
@@ -126,13 +128,19 @@ F64 = torch.float64
 
 
 class Level:
-    """One level of the hierarchy: grid, Legendre tables, SDC matrices, workspace."""
+    """One level of the hierarchy: grid, Legendre tables, SDC matrices, workspace.
+
+    legendre="table" stores the packed P_n^m tables; "recurrence" stores none
+    and lets the Legendre kernels evaluate P_n^m by recurrence
+    (PFSH_LEGENDRE_RECURRENCE; FP64 and FP32 only)."""
 
     def __init__(self, T, nlat, nlon, n_nodes, max_batch=1, radius=6.371e6, omega=7.292e-5,
-                 phibar=9.81 * 1e4, nu=1e5, precision="fp64", device=0):
+                 phibar=9.81 * 1e4, nu=1e5, precision="fp64", device=0, legendre="table"):
+        flag = {"table": 0, "recurrence": LEGENDRE_RECURRENCE}[legendre]
         self.desc = LevelDesc(T, nlat, nlon, n_nodes, max_batch, radius, omega, phibar, nu,
-                              PRECISIONS[precision])
+                              PRECISIONS[precision] | flag)
         self.precision = precision
+        self.legendre = legendre
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
         _check(lib().pfsh_level_create(ctypes.byref(self.desc), device, ctypes.byref(h)),
@@ -175,6 +183,13 @@ class Level:
         """Implicit step of the level's sweeps: "combined" (one solve with L)
         or "split" (physical linear substep, then diffusion substep)."""
         _check(lib().pfsh_level_set_implicit(self._h, self.IMPLICIT[mode]), "pfsh_level_set_implicit")
+
+    def bytes(self):
+        """Device memory of the level: (Legendre tables or their recurrence
+        data, workspace) in bytes."""
+        t, w = ctypes.c_ulonglong(), ctypes.c_ulonglong()
+        _check(lib().pfsh_level_bytes(self._h, ctypes.byref(t), ctypes.byref(w)), "pfsh_level_bytes")
+        return t.value, w.value
 
     # -- diagnostic kernel timing
     KERNELS = {"leg_synth": 0, "ring": 1, "leg_anal": 2, "assemble": 3, "prep": 4,

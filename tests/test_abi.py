@@ -63,6 +63,10 @@ def _desc(**kw):
     ({"nu": -1.0}, -1),
     ({"precision": 3}, -1),
     ({"T": 0}, -2),
+    ({"precision": 0x100}, 0),      # FP64 with the Legendre recurrence
+    ({"precision": 0x101}, 0),      # FP32 with the Legendre recurrence
+    ({"precision": 0x102}, -1),     # BF16x3 has no recurrence mode
+    ({"precision": 0x200}, -1),     # unknown flag
 ])
 def test_desc_validation(L, kw, code):
     d = _desc(**kw)
@@ -82,6 +86,7 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.pfsh_residual(None, 1.0, one, one, one, None, one, 1, None) == -1
     assert L.pfsh_residual_noalloc(None, 1.0, one, one, one, None, one, 1, None) == -1
     assert L.pfsh_level_set_implicit(None, 0) == -1
+    assert L.pfsh_level_bytes(None, None, None) == -1
     assert L.pfsh_restrict(None, None, one, one, 1, None) == -1
     assert L.pfsh_interpolate_add(None, None, one, None, one, 1, None) == -1
     assert L.pfsh_fas_tau(None, None, 1.0, one, one, one, one, one, 1, None) == -1
