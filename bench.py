@@ -492,13 +492,17 @@ def sweep_benchmark(torch, pfsh, inputs, reps=20, rounds=5):
     """The batched fine sweep alone, per transform precision: 16 independent
     seeded states (seeds 300..315, spread initial guess) at the fine level,
     direct launches timed with HIP events (median of `rounds` x `reps` sweeps),
-    and each precision's state after one sweep against the FP64 sweep."""
+    and each precision's state after one sweep against the FP64 sweep.  The
+    FP64 and FP32 levels run again in recurrence mode (no Legendre tables:
+    P_n^m evaluated inside the Legendre kernels); table_bytes is the level's
+    table memory in each mode."""
     Tf, nlf, nof, nnf = FINE
     B = 16
     x0 = torch.from_numpy(inputs.seeded_batch(Tf, range(300, 300 + B), POWER)).to("cuda")
     out, ref = {}, None
-    for prec in ("fp64", "fp32", "bf16x3"):
-        gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=prec)
+    for prec, leg in (("fp64", "table"), ("fp32", "table"), ("bf16x3", "table"),
+                      ("fp64", "recurrence"), ("fp32", "recurrence")):
+        gl = pfsh.Level(Tf, nlf, nof, nnf, max_batch=B, precision=prec, legendre=leg)
         th, fe, fi = gl.space_time(B), gl.space_time(B), gl.space_time(B)
         e, i = gl.rhs(x0)
         th[:, 0] = x0
@@ -520,9 +524,10 @@ def sweep_benchmark(torch, pfsh, inputs, reps=20, rounds=5):
             times.append(a.elapsed_time(b) / reps)
         ms = float(np.median(times))
         sht = 4 * rhs_sht_flops(Tf, nlf, nof, B)
-        out[prec] = {"ms": ms, "sweeps_per_s": 1e3 / ms, "slice_sweeps_per_s": B * 1e3 / ms,
-                     "sht_tflops": sht / (ms * 1e-3) / 1e12,
-                     "rel_err_vs_fp64_one_sweep": rel_err_slices(one, ref)}
+        out[prec if leg == "table" else f"{prec}_recurrence"] = {
+            "ms": ms, "sweeps_per_s": 1e3 / ms, "slice_sweeps_per_s": B * 1e3 / ms,
+            "sht_tflops": sht / (ms * 1e-3) / 1e12,
+            "rel_err_vs_fp64_one_sweep": rel_err_slices(one, ref), "table_bytes": gl.bytes()[0]}
         gl.close()
     return out
 

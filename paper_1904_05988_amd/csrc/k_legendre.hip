@@ -23,6 +23,8 @@
 // k-blocks of a lane in 16 bytes), since the rate of wave load instructions,
 // not bytes, bounds these contractions.  The K loops (mfma_ops.h) run without
 // branches, FP32 in two accumulation chains.
+#include <algorithm>
+
 #include "mfma_ops.h"
 
 namespace pfsh {
@@ -563,42 +565,65 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_rec(
 // PF k-blocks ahead (FP32: two chains by k-block parity).  A k-block row of
 // the LDS tile is padded by one element so that the generating threads, which
 // run over rings, spread over the banks.
-template <class Op, int PF, bool C1>
-__device__ __forceinline__ void anal_rec_slab(const typename Op::R* As, int KS, int rbl,
-                                              const void* __restrict__ G, long long tb,
-                                              long long bstep, int nk, int lane,
-                                              typename Op::C (&acc)[4], typename Op::C (&odd)[4]) {
+// K loop of one wave's NR x (1 + C1) blocks with the A operand in LDS: the
+// lane's element of iteration it at a_lane[it * astep] (second row block 64
+// elements on), the data operand from global memory PF k-blocks ahead.  The
+// structure of mma_loop_rc: a branch-free main loop (prefetch addresses past
+// the end clamped) and a tail; FP32 accumulates in two chains by iteration
+// parity, added at the end.
+template <class Op, int PF, int NR, bool C1>
+__device__ __forceinline__ void mma_loop_lds(const typename Op::R* a_lane, int astep,
+                                             const void* __restrict__ B, long long tb,
+                                             long long bstep, int nk, int lane,
+                                             typename Op::C& acc00, typename Op::C& acc01,
+                                             typename Op::C& acc10, typename Op::C& acc11) {
   constexpr bool SPL = SplitAcc<Op>::value;
   static_assert(!SPL || PF % 2 == 0, "two chains need an even prefetch depth");
+  tb = wave_uniform(tb);
+  bstep = wave_uniform(bstep);
+  nk = __builtin_amdgcn_readfirstlane(nk);
+  if (nk <= 0) return;
+  typename Op::C x00 = {}, x01 = {}, x10 = {}, x11 = {};
   typename Op::A b0[PF], b1[PF];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {
     const long long k = s < nk ? s : nk - 1;
-    b0[s] = Op::load(G, tb + k * bstep, lane);
-    if (C1) b1[s] = Op::load(G, tb + k * bstep + 1, lane);
+    b0[s] = Op::load(B, tb + k * bstep, lane);
+    if (C1) b1[s] = Op::load(B, tb + k * bstep + 1, lane);
   }
-  for (int k0 = 0; k0 < nk; k0 += PF) {
+  auto step = [&](int s, int it) {
+    typename Op::C& c00 = (SPL && (s & 1)) ? x00 : acc00;
+    typename Op::C& c01 = (SPL && (s & 1)) ? x01 : acc01;
+    typename Op::C& c10 = (SPL && (s & 1)) ? x10 : acc10;
+    typename Op::C& c11 = (SPL && (s & 1)) ? x11 : acc11;
+    const typename Op::A a0 = a_lane[it * astep];
+    c00 = Op::mma(a0, b0[s], c00);
+    if (C1) c01 = Op::mma(a0, b1[s], c01);
+    if (NR > 1) {
+      const typename Op::A a1 = a_lane[it * astep + 64];
+      c10 = Op::mma(a1, b0[s], c10);
+      if (C1) c11 = Op::mma(a1, b1[s], c11);
+    }
+  };
+  int k0 = 0;
+  for (; k0 + PF <= nk; k0 += PF) {
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
-      const int kl = k0 + s;
-      if (kl < nk) {
-        const typename Op::A a0 = As[kl * KS + rbl * 64 + lane];
-        const typename Op::A a1 = As[kl * KS + (rbl + 1) * 64 + lane];
-        auto blocks = [&](typename Op::C (&d)[4]) {
-          d[0] = Op::mma(a0, b0[s], d[0]);
-          if (C1) d[1] = Op::mma(a0, b1[s], d[1]);
-          d[2] = Op::mma(a1, b0[s], d[2]);
-          if (C1) d[3] = Op::mma(a1, b1[s], d[3]);
-        };
-        if (SPL && (s & 1))
-          blocks(odd);
-        else
-          blocks(acc);
-      }
-      const long long k = kl + PF < nk ? kl + PF : nk - 1;
-      b0[s] = Op::load(G, tb + k * bstep, lane);
-      if (C1) b1[s] = Op::load(G, tb + k * bstep + 1, lane);
+      step(s, k0 + s);
+      const int kn = k0 + s + PF;
+      const long long k = kn < nk ? kn : nk - 1;
+      b0[s] = Op::load(B, tb + k * bstep, lane);
+      if (C1) b1[s] = Op::load(B, tb + k * bstep + 1, lane);
     }
+  }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s)
+    if (k0 + s < nk) step(s, k0 + s);
+  if constexpr (SPL) {
+    acc00 += x00;
+    acc01 += x01;
+    acc10 += x10;
+    acc11 += x11;
   }
 }
 
@@ -637,7 +662,7 @@ __global__ __launch_bounds__(256) void k_leg_anal_rec(
     cf[3 * threadIdx.x + 1] = b;
     cf[3 * threadIdx.x + 2] = c;
   }
-  C acc[4] = {}, odd[4] = {};
+  C acc[4] = {};
   for (int j0 = 0; j0 < Jp; j0 += SR) {
     const int sr = min(SR, Jp - j0);
     __syncthreads();   // coefficients staged; the previous slab has been read
@@ -654,17 +679,16 @@ __global__ __launch_bounds__(256) void k_leg_anal_rec(
     __syncthreads();
     if (live) {
       const long long tb = ((long long)it.mp * kb2 + j0 / 4) * CBa + cb0;
+      const R* a_lane = As + rbl * 64 + lane;
       if (c1)
-        anal_rec_slab<Op, PF, true>(As, KS, rbl, G, tb, (long long)CBa, sr / 4, lane, acc, odd);
+        mma_loop_lds<Op, PF, 2, true>(a_lane, KS, G, tb, (long long)CBa, sr / 4, lane, acc[0],
+                                      acc[1], acc[2], acc[3]);
       else
-        anal_rec_slab<Op, PF, false>(As, KS, rbl, G, tb, (long long)CBa, sr / 4, lane, acc, odd);
+        mma_loop_lds<Op, PF, 2, false>(a_lane, KS, G, tb, (long long)CBa, sr / 4, lane, acc[0],
+                                       acc[1], acc[2], acc[3]);
     }
   }
   if (!live) return;
-  if constexpr (SplitAcc<Op>::value) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] += odd[b];
-  }
   const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
   const int rb0 = it.tile * 4 + rbl;
 #pragma unroll
@@ -677,6 +701,198 @@ __global__ __launch_bounds__(256) void k_leg_anal_rec(
     for (int v = 0; v < 4; ++v) {
       const int i = rb * 16 + Op::row(lane, v);
       if (i < q.np) Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (R)acc[blk][v];
+    }
+  }
+}
+
+// The same contractions with the whole operand block generated once per
+// workgroup and kept in LDS while the workgroup runs every column tile: the
+// recurrence then costs once per (order, ring block) or (order, degree tile)
+// instead of once per column tile.  Used when the block fits in LDS (T up to
+// 511 for the synthesis; the analysis tile of 64 degrees x all rings up to
+// T767 in FP32 and T255 in FP64); the kernels above serve the rest.
+
+// Synthesis: workgroup = MC orders of one parity x one block of 16 NRB rings,
+// wave w the column of order m0 + w ([k-block][NRB row blocks][64 lanes],
+// 16 NRB rings x all degrees).  Lane (ring r, chunk h) generates 64 / (16
+// NRB) chunks per round; the coefficient staging and then the output exchange
+// share one LDS region.  NRB = 2 halves the data-operand loads per MFMA where
+// the columns fit.
+template <class Op, int MC, int PF, int NRB>
+__global__ __launch_bounds__(64 * MC) void k_leg_synth_rec_cols(
+    const double* __restrict__ seeds, const double* __restrict__ rec, const double* __restrict__ mu,
+    const void* __restrict__ X, typename Op::R* __restrict__ F4, const MPInfo* __restrict__ mpi,
+    const WorkItem* __restrict__ items, int nitems, int nrb, int kbmax, int CBs, int CBn,
+    int ncols, int nf, int J, int Jp, int T, int Lp) {
+  typedef typename Op::R R;
+  typedef typename Op::C C;
+  constexpr int SM = MC + 1, RW = 16 * NRB;        // rings per workgroup
+  constexpr int CPR = 64 / RW, GEN = CPR * kRecChunk;   // chunks and degrees per round
+  extern __shared__ unsigned char smem_raw[];
+  R* cols = reinterpret_cast<R*>(smem_raw);                          // [MC][kbmax][NRB][64]
+  unsigned char* aux = smem_raw + (size_t)MC * kbmax * NRB * 64 * sizeof(R);
+  double* coef = reinterpret_cast<double*>(aux);                     // [MC][GEN][3], then
+  R* stage = reinterpret_cast<R*>(aux);                              // [16][32][SM]
+  int item, rbk;
+  if (!xcd_group(nitems, nrb, item, rbk)) return;
+  const WorkItem it = items[item];
+  const int p = it.mp & 1, m0 = it.mp >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = m0 + wave;
+  R* P = cols + (size_t)wave * kbmax * NRB * 64;
+  int kbS = 0;
+  long long xS = 0;
+  if (m <= T) {
+    const MPInfo q = mpi[2 * m + p];
+    kbS = q.kbS;
+    xS = q.xS;
+    const int r = lane % RW, h = lane / RW, j = rbk * RW + r;
+    const double x = j < J ? mu[j] : 0.0, x2 = x * x;
+    const int nch = rec_chunks(q.np), ebase = ext_off(T, m) + p;
+    double* cf = coef + (size_t)wave * GEN * 3;
+    for (int g0 = 0; g0 < q.np; g0 += GEN) {
+      wave_lds_sync();   // the previous round's coefficient reads are done
+      for (int l = lane; l < GEN; l += 64) {
+        const int i = g0 + l;
+        double a = 0.0, b = 0.0, c = 0.0;
+        if (i >= 1 && i < q.np) {
+          const double* rc = rec + (size_t)(ebase + 2 * (i - 1)) * 4;
+          a = rc[0];
+          b = rc[1];
+          c = rc[2];
+        }
+        cf[3 * l] = a;
+        cf[3 * l + 1] = b;
+        cf[3 * l + 2] = c;
+      }
+      wave_lds_sync();
+      const int ch = g0 / kRecChunk + h;
+      rec_chunk(seeds + ((size_t)(q.seed + ch) * Jp + j) * 2, ch < nch && j < J, x2, cf,
+                h * kRecChunk, ch * kRecChunk, q.np, [&](int t, double v) {
+                  const int i = ch * kRecChunk + t;
+                  if (i < 4 * kbS)
+                    P[((i >> 2) * NRB + r / 16) * 64 + (i & 3) * 16 + (r & 15)] = (R)v;
+                });
+    }
+    wave_lds_sync();
+  }
+  for (int cb0 = 0; cb0 < CBn; cb0 += 2) {
+    const bool c1 = cb0 + 1 < CBn;
+    C acc[4] = {};
+    if (kbS > 0) {   // highest degrees first
+      const long long tb = xS + cb0 + (long long)(kbS - 1) * CBs;
+      const R* a_lane = P + (size_t)(kbS - 1) * NRB * 64 + lane;
+      if (c1)
+        mma_loop_lds<Op, PF, NRB, true>(a_lane, -NRB * 64, X, tb, -(long long)CBs, kbS, lane,
+                                        acc[0], acc[1], acc[2], acc[3]);
+      else
+        mma_loop_lds<Op, PF, NRB, false>(a_lane, -NRB * 64, X, tb, -(long long)CBs, kbS, lane,
+                                         acc[0], acc[1], acc[2], acc[3]);
+    }
+    // exchange one 16-ring block at a time
+#pragma unroll
+    for (int hb = 0; hb < NRB; ++hb) {
+      __syncthreads();   // the exchange region is free (coefficients, previous round)
+#pragma unroll
+      for (int cbk = 0; cbk < 2; ++cbk) {
+        const int cc = cbk * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          stage[(Op::row(lane, v) * 32 + cc) * SM + wave] = (R)acc[2 * hb + cbk][v];
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < 16 * 16; t += 64 * MC) {
+        const int rw = t >> 4, cp = t & 15;
+        const int j = rbk * RW + hb * 16 + rw, c = cb0 * 16 + 2 * cp;
+        if (j >= J || c >= ncols) continue;
+        const int bf = c >> 1, f = bf % nf, b = bf / nf;
+        R out[2 * MC];
+        const R* re = stage + (rw * 32 + 2 * cp) * SM;
+        const R* im = re + SM;
+#pragma unroll
+        for (int mi = 0; mi < MC; ++mi) {
+          out[2 * mi] = re[mi];
+          out[2 * mi + 1] = im[mi];
+        }
+        store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
+      }
+    }
+  }
+}
+
+// Analysis: workgroup = one (m, p) and 64 degrees with all rings in LDS;
+// after the generation each wave runs its two degree blocks against every
+// fourth pair of column blocks.
+template <class Op, int PF, int NW>
+__global__ __launch_bounds__(64 * NW) void k_leg_anal_rec_cols(
+    const double* __restrict__ seeds, const double* __restrict__ rec, const double* __restrict__ mu,
+    const void* __restrict__ G, typename Op::R* __restrict__ Y, const MPInfo* __restrict__ mpi,
+    const WorkItem* __restrict__ items, int nitems, int kb2, int CBa, int CBn, int ncols, int Kx,
+    int J, int Jp, int T) {
+  typedef typename Op::R R;
+  typedef typename Op::C C;
+  constexpr int KS = 4 * 64 + 1;
+  extern __shared__ unsigned char smem_raw[];
+  R* As = reinterpret_cast<R*>(smem_raw);                                           // [Jp/4][KS]
+  double* cf = reinterpret_cast<double*>(smem_raw + (size_t)(Jp / 4) * KS * sizeof(R));  // [64][3]
+  int item, ct;
+  if (!xcd_tile(nitems, 1, item, ct)) return;
+  const WorkItem it = items[item];
+  const MPInfo q = mpi[it.mp];
+  if (it.tile * 4 >= q.rbA) return;                    // padding item (whole workgroup)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int deg0 = it.tile * 64, nch = rec_chunks(q.np), ebase = ext_off(T, q.m) + q.p;
+  if (threadIdx.x < 64) {
+    const int i = deg0 + threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (i >= 1 && i < q.np) {
+      const double* rc = rec + (size_t)(ebase + 2 * (i - 1)) * 4;
+      a = rc[0];
+      b = rc[1];
+      c = rc[2];
+    }
+    cf[3 * threadIdx.x] = a;
+    cf[3 * threadIdx.x + 1] = b;
+    cf[3 * threadIdx.x + 2] = c;
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < 2 * Jp; task += 64 * NW) {
+    const int j = task % Jp, hh = task / Jp, ch = 2 * it.tile + hh;
+    const double x = j < J ? mu[j] : 0.0;
+    R* dst = As + (j >> 2) * KS + (j & 3) * 16;
+    rec_chunk(seeds + ((size_t)(q.seed + ch) * Jp + j) * 2, ch < nch && j < J, x * x, cf,
+              hh * kRecChunk, ch * kRecChunk, q.np, [&](int t, double v) {
+                const int dl = hh * kRecChunk + t;
+                dst[(dl >> 4) * 64 + (dl & 15)] = (R)v;
+              });
+  }
+  __syncthreads();
+  // wave w: degree blocks 2 ((w / 2) % 2) + {0, 1}; the NW / 2 waves of one
+  // degree pair take column pairs 2 (w % 2) + 4 (w / 4) in steps of NW blocks
+  const int rbl = ((wave >> 1) & 1) * 2, rb0 = it.tile * 4 + rbl;
+  const int base = ext_off(T, q.m) + (q.p ? npar(T, q.m, 0) : 0);   // this parity's run
+  for (int cb0 = (wave & 1) * 2 + (wave >> 2) * 4; cb0 < CBn; cb0 += NW) {
+    const bool c1 = cb0 + 1 < CBn;
+    C acc[4] = {};
+    const long long tb = (long long)it.mp * kb2 * CBa + cb0;
+    const R* a_lane = As + rbl * 64 + lane;
+    if (c1)
+      mma_loop_lds<Op, PF, 2, true>(a_lane, KS, G, tb, (long long)CBa, Jp / 4, lane, acc[0],
+                                    acc[1], acc[2], acc[3]);
+    else
+      mma_loop_lds<Op, PF, 2, false>(a_lane, KS, G, tb, (long long)CBa, Jp / 4, lane, acc[0],
+                                     acc[1], acc[2], acc[3]);
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const int rb = rb0 + (blk >> 1), cb = cb0 + (blk & 1);
+      if ((blk & 1) && !c1) continue;
+      const int c = cb * 16 + (lane & 15);
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = rb * 16 + Op::row(lane, v);
+        if (i < q.np) Y[((size_t)(c >> 1) * Kx + base + i) * 2 + (c & 1)] = (R)acc[blk][v];
+      }
     }
   }
 }
@@ -720,6 +936,50 @@ static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   hipLaunchKernelGGL((k_leg_anal<Op, PF, SHAPE>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s,
                      lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
                      nct, lv->kb2, lv->kb2g, lv->CBa, CBn, ncols, lv->Kx, lv->T);
+  return hipGetLastError();
+}
+
+// LDS of the generate-once recurrence kernels (0: does not fit, take the
+// per-column-tile kernels)
+static size_t synth_rec_cols_lds(const pfsh_level* lv, int nrb) {
+  const size_t rsz = lv->op == OP_F64 ? 8 : 4;
+  const int MC = lv->MC, kbmax = (npar(lv->T, 0, 0) + 3) / 4;
+  const size_t aux = std::max((size_t)MC * (4 / nrb) * kRecChunk * 3 * 8,
+                              (size_t)16 * 32 * (MC + 1) * rsz);
+  const size_t b = (size_t)MC * kbmax * nrb * 64 * rsz + aux;
+  return b <= 160 * 1024 ? b : 0;
+}
+static size_t anal_rec_cols_lds(const pfsh_level* lv) {
+  const size_t rsz = lv->op == OP_F64 ? 8 : 4;
+  const size_t b = (size_t)(lv->Jp / 4) * (4 * 64 + 1) * rsz + 64 * 3 * 8;
+  return b <= 160 * 1024 ? b : 0;
+}
+
+template <class Op, int NRB>
+static hipError_t synth_rec_cols_impl(const pfsh_level* lv, int ncols, int nf, size_t shm,
+                                      hipStream_t s) {
+  typedef typename Op::R R;
+  constexpr int MC = Op::KIND == OP_F64 ? 4 : 8;
+  const int CBn = (ncols + 15) / 16, nrb = lv->Jp / (16 * NRB);
+  const int kbmax = (npar(lv->T, 0, 0) + 3) / 4;
+  (void)hipFuncSetAttribute((const void*)k_leg_synth_rec_cols<Op, MC, 4, NRB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_leg_synth_rec_cols<Op, MC, 4, NRB>), dim3(xcd_grid(lv->nitemsS, nrb)),
+                     dim3(64 * MC), shm, s, lv->seeds_d, lv->rec_d, lv->mu_d, lv->X, (R*)lv->F4,
+                     lv->mp_d, lv->itemsS, lv->nitemsS, nrb, kbmax, lv->CBs, CBn, ncols, nf,
+                     lv->J, lv->Jp, lv->T, lv->Lp);
+  return hipGetLastError();
+}
+
+template <class Op, int NW>
+static hipError_t anal_rec_cols_impl(const pfsh_level* lv, int ncols, size_t shm, hipStream_t s) {
+  typedef typename Op::R R;
+  const int CBn = (ncols + 15) / 16;
+  (void)hipFuncSetAttribute((const void*)k_leg_anal_rec_cols<Op, 4, NW>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_leg_anal_rec_cols<Op, 4, NW>), dim3(xcd_grid(lv->nitemsA, 1)), dim3(64 * NW), shm,
+                     s, lv->seeds_d, lv->rec_d, lv->mu_d, lv->G, (R*)lv->Y, lv->mp_d, lv->itemsA,
+                     lv->nitemsA, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->J, lv->Jp, lv->T);
   return hipGetLastError();
 }
 
@@ -767,9 +1027,20 @@ int leg_variant_count(int op, int stage) {
 }
 
 hipError_t launch_leg_synth(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
-  if (lv->rec_mode)
+  if (lv->rec_mode) {
+    // variant 0: generate-once kernel, 32 rings per workgroup where they fit,
+    // else 16; 1: per-column-tile slabs; 2: generate-once with 16 rings
+    const int v = lv->variant[TS_SYNTH][tune_bucket((ncols + 15) / 16)];
+    const size_t shm2 = synth_rec_cols_lds(lv, 2), shm1 = synth_rec_cols_lds(lv, 1);
+    if (v == 0 && shm2)
+      return lv->op == OP_F64 ? synth_rec_cols_impl<OpF64, 2>(lv, ncols, nf, shm2, s)
+                              : synth_rec_cols_impl<OpF32, 2>(lv, ncols, nf, shm2, s);
+    if (v != 1 && shm1)
+      return lv->op == OP_F64 ? synth_rec_cols_impl<OpF64, 1>(lv, ncols, nf, shm1, s)
+                              : synth_rec_cols_impl<OpF32, 1>(lv, ncols, nf, shm1, s);
     return lv->op == OP_F64 ? synth_rec_impl<OpF64>(lv, ncols, nf, s)
                             : synth_rec_impl<OpF32>(lv, ncols, nf, s);
+  }
   const int v = lv->variant[TS_SYNTH][tune_bucket((ncols + 15) / 16)];
   switch (lv->op) {
     case OP_F64:
@@ -815,8 +1086,16 @@ static hipError_t anal_variant(const pfsh_level* lv, int v, int ncols, hipStream
 }
 
 hipError_t launch_leg_anal(const pfsh_level* lv, int ncols, int /*nf*/, hipStream_t s) {
-  if (lv->rec_mode)
+  if (lv->rec_mode) {
+    const size_t shm = anal_rec_cols_lds(lv);
+    const int v = lv->variant[TS_ANAL][tune_bucket((ncols + 15) / 16)];
+    if (shm && v != 1)
+      return lv->op == OP_F64 ? (v == 0 ? anal_rec_cols_impl<OpF64, 8>(lv, ncols, shm, s)
+                                        : anal_rec_cols_impl<OpF64, 4>(lv, ncols, shm, s))
+                              : (v == 0 ? anal_rec_cols_impl<OpF32, 8>(lv, ncols, shm, s)
+                                        : anal_rec_cols_impl<OpF32, 4>(lv, ncols, shm, s));
     return lv->op == OP_F64 ? anal_rec_impl<OpF64>(lv, ncols, s) : anal_rec_impl<OpF32>(lv, ncols, s);
+  }
   const int v = lv->variant[TS_ANAL][tune_bucket((ncols + 15) / 16)];
   switch (lv->op) {
     case OP_F64: return anal_variant<OpF64>(lv, v, ncols, s);

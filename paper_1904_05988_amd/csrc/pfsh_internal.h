@@ -180,8 +180,8 @@ void build_tables(pfsh_level* lv, std::vector<unsigned char>& tabS, std::vector<
 // fills q.seed of every (m, p).  seeds: 2 doubles per (chunk, padded ring).
 void build_recurrence(pfsh_level* lv, std::vector<double>& seeds, std::vector<double>& rec);
 
-// Kernel variants of a stage on this level (1 for the Legendre stages and the
-// sweep path in recurrence mode).
+// Kernel variants of a stage on this level (recurrence mode: 2 per Legendre
+// stage, generate-once and per-column-tile; 1 sweep path).
 int variant_count(const pfsh_level* lv, int stage);
 
 // ------------------------------------------------------------- launchers

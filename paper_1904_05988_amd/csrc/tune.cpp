@@ -11,7 +11,8 @@ int ring_variant_count();
 
 int variant_count(const pfsh_level* lv, int stage) {
   if (stage == TS_RING) return ring_variant_count();
-  if (lv->rec_mode) return 1;   // one recurrence kernel per Legendre stage, no fused node
+  // recurrence mode: generate-once or per-column-tile kernels, no fused node
+  if (lv->rec_mode) return stage == TS_FUSE ? 1 : 3;
   if (stage == TS_FUSE) return 2;
   return leg_variant_count(lv->op, stage);
 }

@@ -40,9 +40,16 @@ def _rec(T, nlat, nlon, nn=3, B=2, precision="fp64"):
     return pfsh.Level(T, nlat, nlon, nn, max_batch=B, precision=precision, legendre="recurrence")
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("T,nlat,nlon", GRIDS)
-def test_sh_synthesis_and_analysis_match_oracle(T, nlat, nlon):
+def test_sh_synthesis_and_analysis_match_oracle(T, nlat, nlon, variant):
+    """Variant 0: the generate-once kernels (synthesis with 32 rings per
+    workgroup, analysis with 8 waves); 1: one recurrence per column tile; 2:
+    generate-once with 16 rings (synthesis) and 4 waves (analysis)."""
     gl = _rec(T, nlat, nlon)
+    for b in (1, 2):
+        gl.set_variant("synth", b, variant)
+        gl.set_variant("anal", b, variant)
     g = sht.Grid(T, nlat, nlon)
     rng = np.random.default_rng(7 + T)
     nf = 5
@@ -59,9 +66,15 @@ def test_sh_synthesis_and_analysis_match_oracle(T, nlat, nlon):
         assert np.abs(back[f] - ref).max() <= 1e-12 * np.abs(ref).max(), ("analysis", f)
 
 
-@pytest.mark.parametrize("T,nlat,nlon,B", [(15, 24, 48, 3), (30, 48, 96, 2), (63, 96, 192, 5)])
-def test_rhs_matches_oracle(T, nlat, nlon, B):
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("T,nlat,nlon,B", [(15, 24, 48, 3), (30, 48, 96, 2), (63, 96, 192, 5),
+                                           (31, 48, 96, 13)])
+def test_rhs_matches_oracle(T, nlat, nlon, B, variant):
+    """B = 13: 9 analysis and 7 synthesis column blocks, so every wave of the
+    generate-once kernels runs more than one (ragged) column round."""
     gl = _rec(T, nlat, nlon, B=B)
+    gl.set_variant("synth", B, variant)
+    gl.set_variant("anal", B, variant)
     ol = swe.Level(T, nlat, nlon)
     states = seeded(T, range(20, 20 + B))
     fe, fi = gl.rhs(to_dev(states))
