@@ -16,8 +16,9 @@ plain FP64 is timed next to it, and the states of the two are compared after
 every iteration (and against serial FP64 SDC on the same time steps, the
 collocation solution PFASST converges to).
 Iterations are replayed from captured HIP graphs.  Every kernel of every level
-is timed with HIP events around its launches in a second pass over the same
-blocks with direct launches; the roofline line names the kernel with the
+is timed in a second pass over the same blocks with direct launches, each
+launch by events attached to the kernel itself (its own start and end
+timestamps, no launch gap); the roofline line names the kernel with the
 largest time per block, against the bound (MFMA or HBM) its algorithmic work
 per launch sets.  The standalone batched SH round trip (synthesis + analysis)
 is timed as well.  The oracle is timed on the host cores on a bounded sample,
@@ -360,7 +361,7 @@ def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
         if profile:
             for _, lv in named:
                 lv.profile(False)
-            # every launch of every level, ms per block (event-bracketed, no graphs),
+            # every launch of every level, ms per block (kernel timestamps, no graphs),
             # and the same split by the batch of the launch
             per_level, groups = {}, []
             B = N_TS * MEMBERS
@@ -675,7 +676,7 @@ def main():
 
     r64 = run_gpu(args, "fp64", 0, torch, pfsh, inputs)
     rmx = run_gpu(args, args.mixed, args.n64, torch, pfsh, inputs)
-    # the same timed blocks again with direct launches and HIP events per kernel
+    # the same timed blocks again with direct launches and per-kernel timestamps
     rpr = run_gpu(args, args.mixed, args.n64, torch, pfsh, inputs, profile=True)
     s64 = run_states(args, "fp64", 0, torch, pfsh, inputs)
     smx = run_states(args, args.mixed, args.n64, torch, pfsh, inputs)

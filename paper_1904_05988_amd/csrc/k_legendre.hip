@@ -904,7 +904,7 @@ static inline unsigned xcd_grid(int nitems, int nct) {
 template <class Op, int MC, int PF, int HS = 32>
 static hipError_t synth_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = (CBn + 1) / 2, ntile = (lv->RB + 1) / 2;
-  hipLaunchKernelGGL((k_leg_synth<Op, MC, PF, HS>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+  PFSH_LAUNCH(lv, (k_leg_synth<Op, MC, PF, HS>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
                      dim3(64 * MC), 0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d,
                      lv->itemsS, lv->nitemsS, ntile, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J,
                      lv->T, lv->Lp);
@@ -914,7 +914,7 @@ static hipError_t synth_impl(const pfsh_level* lv, int ncols, int nf, hipStream_
 template <class Op, int MC, int PF>
 static hipError_t synth_t4_impl(const pfsh_level* lv, int ncols, int nf, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4, ntile = (lv->RB + 3) / 4;
-  hipLaunchKernelGGL((k_leg_synth_t4<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+  PFSH_LAUNCH(lv, (k_leg_synth_t4<Op, MC, PF>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
                      dim3(64 * MC), 0, s, lv->tabS, lv->X, (typename Op::R*)lv->F4, lv->mp_d,
                      lv->itemsS, lv->nitemsS, ntile, nct, lv->RB, lv->CBs, CBn, ncols, nf, lv->J,
                      lv->T, lv->Lp);
@@ -924,7 +924,7 @@ static hipError_t synth_t4_impl(const pfsh_level* lv, int ncols, int nf, hipStre
 template <class Op, int PF>
 static hipError_t anal_tall_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = (CBn + 3) / 4;
-  hipLaunchKernelGGL((k_leg_anal_tall<Op, PF>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(128), 0, s,
+  PFSH_LAUNCH(lv, (k_leg_anal_tall<Op, PF>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(128), 0, s,
                      lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
                      nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->T);
   return hipGetLastError();
@@ -933,7 +933,7 @@ static hipError_t anal_tall_impl(const pfsh_level* lv, int ncols, hipStream_t s)
 template <class Op, int PF, int SHAPE>
 static hipError_t anal_impl(const pfsh_level* lv, int ncols, hipStream_t s) {
   const int CBn = (ncols + 15) / 16, nct = SHAPE == 0 ? (CBn + 3) / 4 : (CBn + 1) / 2;
-  hipLaunchKernelGGL((k_leg_anal<Op, PF, SHAPE>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s,
+  PFSH_LAUNCH(lv, (k_leg_anal<Op, PF, SHAPE>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), 0, s,
                      lv->tabA, lv->G, (typename Op::R*)lv->Y, lv->mp_d, lv->itemsA, lv->nitemsA,
                      nct, lv->kb2, lv->kb2g, lv->CBa, CBn, ncols, lv->Kx, lv->T);
   return hipGetLastError();
@@ -964,7 +964,7 @@ static hipError_t synth_rec_cols_impl(const pfsh_level* lv, int ncols, int nf, s
   const int kbmax = (npar(lv->T, 0, 0) + 3) / 4;
   (void)hipFuncSetAttribute((const void*)k_leg_synth_rec_cols<Op, MC, 4, NRB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_leg_synth_rec_cols<Op, MC, 4, NRB>), dim3(xcd_grid(lv->nitemsS, nrb)),
+  PFSH_LAUNCH(lv, (k_leg_synth_rec_cols<Op, MC, 4, NRB>), dim3(xcd_grid(lv->nitemsS, nrb)),
                      dim3(64 * MC), shm, s, lv->seeds_d, lv->rec_d, lv->mu_d, lv->X, (R*)lv->F4,
                      lv->mp_d, lv->itemsS, lv->nitemsS, nrb, kbmax, lv->CBs, CBn, ncols, nf,
                      lv->J, lv->Jp, lv->T, lv->Lp);
@@ -977,7 +977,7 @@ static hipError_t anal_rec_cols_impl(const pfsh_level* lv, int ncols, size_t shm
   const int CBn = (ncols + 15) / 16;
   (void)hipFuncSetAttribute((const void*)k_leg_anal_rec_cols<Op, 4, NW>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_leg_anal_rec_cols<Op, 4, NW>), dim3(xcd_grid(lv->nitemsA, 1)), dim3(64 * NW), shm,
+  PFSH_LAUNCH(lv, (k_leg_anal_rec_cols<Op, 4, NW>), dim3(xcd_grid(lv->nitemsA, 1)), dim3(64 * NW), shm,
                      s, lv->seeds_d, lv->rec_d, lv->mu_d, lv->G, (R*)lv->Y, lv->mp_d, lv->itemsA,
                      lv->nitemsA, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->J, lv->Jp, lv->T);
   return hipGetLastError();
@@ -992,7 +992,7 @@ static hipError_t synth_rec_impl(const pfsh_level* lv, int ncols, int nf, hipStr
                      (size_t)MC * 2 * kRecChunk * 3 * sizeof(double);
   (void)hipFuncSetAttribute((const void*)k_leg_synth_rec<Op, MC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_leg_synth_rec<Op, MC>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
+  PFSH_LAUNCH(lv, (k_leg_synth_rec<Op, MC>), dim3(xcd_grid(lv->nitemsS, ntile * nct)),
                      dim3(64 * MC), shm, s, lv->seeds_d, lv->rec_d, lv->mu_d, lv->X,
                      (R*)lv->F4, lv->mp_d, lv->itemsS, lv->nitemsS, ntile, nct, lv->CBs, CBn,
                      ncols, nf, lv->J, lv->Jp, lv->T, lv->Lp);
@@ -1007,7 +1007,7 @@ static hipError_t anal_rec_impl(const pfsh_level* lv, int ncols, hipStream_t s) 
   const size_t shm = (size_t)(SR / 4) * (4 * 64 + 1) * sizeof(R) + (size_t)64 * 3 * sizeof(double);
   (void)hipFuncSetAttribute((const void*)k_leg_anal_rec<Op, 4>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_leg_anal_rec<Op, 4>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), shm, s,
+  PFSH_LAUNCH(lv, (k_leg_anal_rec<Op, 4>), dim3(xcd_grid(lv->nitemsA, nct)), dim3(256), shm, s,
                      lv->seeds_d, lv->rec_d, lv->mu_d, lv->G, (R*)lv->Y, lv->mp_d, lv->itemsA,
                      lv->nitemsA, nct, lv->kb2, lv->CBa, CBn, ncols, lv->Kx, lv->J, lv->Jp, lv->T);
   return hipGetLastError();

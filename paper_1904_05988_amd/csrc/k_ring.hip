@@ -525,7 +525,7 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
       (void)hipFuncSetAttribute((const void*)k_ring_rhs<Op, N, CAP, NT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     const int per = (lv->J * count + 7) / 8;
-    hipLaunchKernelGGL((k_ring_rhs<Op, N, CAP, NT>), dim3(8 * per), dim3(NT), shm, s,
+    PFSH_LAUNCH(lv, (k_ring_rhs<Op, N, CAP, NT>), dim3(8 * per), dim3(NT), shm, s,
                        (const R*)lv->F4, lv->G, lv->mu_d, lv->w_d, tw, lv->J, count, lv->L, lv->Lp,
                        lv->kb2g, lv->CBa, 2.0 * lv->d.omega);
   } else if (kind == 1) {
@@ -533,14 +533,14 @@ static hipError_t ring_launch(int kind, const pfsh_level* lv, int count, const d
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_synth<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ring_synth<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
+    PFSH_LAUNCH(lv, (k_ring_synth<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
                        (const R*)lv->F4, gout, tw, lv->J, lv->L, lv->Lp, count);
   } else {
     shm = (size_t)4 * sig_stride(N) * sizeof(cpx<R>) + twl;
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)k_ring_anal<Op, N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ring_anal<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
+    PFSH_LAUNCH(lv, (k_ring_anal<Op, N>), dim3(lv->J, (count + 3) / 4), dim3(256), shm, s,
                        gin, lv->G, lv->w_d, tw, lv->J, lv->L, count, lv->kb2g, lv->CBa);
   }
   return hipGetLastError();

@@ -992,15 +992,15 @@ hipError_t launch_prep_rhs(const pfsh_level* lv, const double* state, long long 
   dim3 grid(lv->L, (batch + 1) / 2);
   switch (lv->op) {
     case OP_F64:
-      hipLaunchKernelGGL(k_prep_rhs<OpF64>, grid, dim3(128), 0, s, state, sstride, f_impl,
+      PFSH_LAUNCH(lv, k_prep_rhs<OpF64>, grid, dim3(128), 0, s, state, sstride, f_impl,
                          fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     case OP_F32:
-      hipLaunchKernelGGL(k_prep_rhs<OpF32>, grid, dim3(128), 0, s, state, sstride, f_impl,
+      PFSH_LAUNCH(lv, k_prep_rhs<OpF32>, grid, dim3(128), 0, s, state, sstride, f_impl,
                          fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
       break;
     default:
-      hipLaunchKernelGGL(k_prep_rhs<OpBF3>, grid, dim3(128), 0, s, state, sstride, f_impl,
+      PFSH_LAUNCH(lv, k_prep_rhs<OpBF3>, grid, dim3(128), 0, s, state, sstride, f_impl,
                          fstride, lv->X, lv->mp_d, lv->T, lv->CBs, batch, phys_of(lv));
   }
   return hipGetLastError();
@@ -1010,15 +1010,15 @@ hipError_t launch_prep_scalar(const pfsh_level* lv, const double* spec, int nfie
   dim3 grid(lv->L, nfields);
   switch (lv->op) {
     case OP_F64:
-      hipLaunchKernelGGL(k_prep_scalar<OpF64>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
+      PFSH_LAUNCH(lv, k_prep_scalar<OpF64>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
                          lv->T, lv->CBs);
       break;
     case OP_F32:
-      hipLaunchKernelGGL(k_prep_scalar<OpF32>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
+      PFSH_LAUNCH(lv, k_prep_scalar<OpF32>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
                          lv->T, lv->CBs);
       break;
     default:
-      hipLaunchKernelGGL(k_prep_scalar<OpBF3>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
+      PFSH_LAUNCH(lv, k_prep_scalar<OpBF3>, grid, dim3(128), 0, s, spec, lv->X, lv->mp_d,
                          lv->T, lv->CBs);
   }
   return hipGetLastError();
@@ -1027,10 +1027,10 @@ hipError_t launch_prep_scalar(const pfsh_level* lv, const double* spec, int nfie
 hipError_t launch_unpack_scalar(const pfsh_level* lv, double* spec, int nfields, hipStream_t s) {
   const long long work = (long long)nfields * lv->K;
   if (lv->op == OP_F64)
-    hipLaunchKernelGGL(k_unpack_scalar<double>, dim3(nblocks(work, 256)), dim3(256), 0, s,
+    PFSH_LAUNCH(lv, k_unpack_scalar<double>, dim3(nblocks(work, 256)), dim3(256), 0, s,
                        (const double*)lv->Y, spec, lv->T, nfields);
   else
-    hipLaunchKernelGGL(k_unpack_scalar<float>, dim3(nblocks(work, 256)), dim3(256), 0, s,
+    PFSH_LAUNCH(lv, k_unpack_scalar<float>, dim3(nblocks(work, 256)), dim3(256), 0, s,
                        (const float*)lv->Y, spec, lv->T, nfields);
   return hipGetLastError();
 }
@@ -1039,10 +1039,10 @@ hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fstri
                            hipStream_t s) {
   dim3 grid(lv->L, batch);
   if (lv->op == OP_F64)
-    hipLaunchKernelGGL(k_assemble<double>, grid, dim3(128), 0, s, (const double*)lv->Y, f_expl,
+    PFSH_LAUNCH(lv, k_assemble<double>, grid, dim3(128), 0, s, (const double*)lv->Y, f_expl,
                        fstride, lv->T, lv->d.radius);
   else
-    hipLaunchKernelGGL(k_assemble<float>, grid, dim3(128), 0, s, (const float*)lv->Y, f_expl,
+    PFSH_LAUNCH(lv, k_assemble<float>, grid, dim3(128), 0, s, (const float*)lv->Y, f_expl,
                        fstride, lv->T, lv->d.radius);
   return hipGetLastError();
 }
@@ -1050,7 +1050,7 @@ hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fstri
 hipError_t launch_implicit_solve(const pfsh_level* lv, double beta, const double* b, double* x,
                                  int batch, hipStream_t s) {
   const long long work = (long long)batch * lv->K;
-  hipLaunchKernelGGL(k_implicit_solve, dim3(nblocks(work, 256)), dim3(256), 0, s, b, x, lv->T,
+  PFSH_LAUNCH(lv, k_implicit_solve, dim3(nblocks(work, 256)), dim3(256), 0, s, b, x, lv->T,
                      batch, beta, phys_of(lv));
   return hipGetLastError();
 }
@@ -1076,7 +1076,7 @@ static hipError_t sweep_step_nd(const pfsh_level* lv, int node, int asm_node, do
     (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN, ND>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   // order pairs (g, L - g): order 0, L/2 - 1 or (L-1)/2 pairs, and order L/2 for even L
-  hipLaunchKernelGGL((k_sweep_step<Op, NN, ND>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm,
+  PFSH_LAUNCH(lv, (k_sweep_step<Op, NN, ND>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm,
                      s, th, fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d,
                      lv->T, lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
                      SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});
@@ -1113,7 +1113,7 @@ static hipError_t node_fused_impl(const pfsh_level* lv, int node, int asm_node, 
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)k_node_fused<Op, NN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_node_fused<Op, NN>), dim3(lv->L), dim3(1024), shm, s, th, fe, fi, tau, lv->S,
+  PFSH_LAUNCH(lv, (k_node_fused<Op, NN>), dim3(lv->L), dim3(1024), shm, s, th, fe, fi, tau, lv->S,
                      lv->tabA, lv->G, lv->tabS, (R*)lv->F4, lv->mp_d, lv->T, lv->J, lv->Lp, lv->kb2,
                      lv->CBa, lv->RB, kbmax, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
                      SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});

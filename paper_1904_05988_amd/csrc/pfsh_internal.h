@@ -2,6 +2,7 @@
 // kernel launchers shared by the host API and the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -100,6 +101,7 @@ inline int tune_bucket(int n) {
   while (b < kTuneBuckets - 1 && (1 << b) < n) ++b;
   return b;
 }
+struct ProfScope;
 }  // namespace pfsh
 
 struct pfsh_level {
@@ -143,30 +145,58 @@ struct pfsh_level {
   mutable bool prof_on = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[PFSH_K_COUNT];
   mutable std::vector<int> prof_batch[PFSH_K_COUNT];   // batch of each bracketed launch
+  mutable pfsh::ProfScope* prof_open = nullptr;         // the launch being profiled (ProfScope)
 };
 
 namespace pfsh {
 
-// Event bracket of one launch when profiling is on: begin() records the start
-// event before the launch, end() the stop event after it.
+// Timing of one kernel launch when profiling is on: the scope opens a pair of
+// events on the level, and the next launch through PFSH_LAUNCH on that level
+// takes them as the kernel's own start and end timestamps
+// (hipExtLaunchKernelGGL), so the measured time is the kernel's alone, without
+// the gap between launches.  A scope whose launch did not happen drops its
+// events.
 struct ProfScope {
   const pfsh_level* lv;
   int id;
   hipStream_t s;
   int batch;
   hipEvent_t b = nullptr, e = nullptr;
+  bool used = false;
+  ProfScope* prev = nullptr;
   ProfScope(const pfsh_level* l, int k, hipStream_t st, int nb = 0) : lv(l), id(k), s(st), batch(nb) {
     if (!lv->prof_on) return;
-    if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) { b = e = nullptr; return; }
-    (void)hipEventRecord(b, s);
+    if (hipEventCreate(&b) != hipSuccess) { b = nullptr; return; }
+    if (hipEventCreate(&e) != hipSuccess) { (void)hipEventDestroy(b); b = e = nullptr; return; }
+    prev = lv->prof_open;
+    lv->prof_open = this;
   }
   ~ProfScope() {
     if (!b) return;
-    (void)hipEventRecord(e, s);
-    lv->prof[id].push_back({b, e});
-    lv->prof_batch[id].push_back(batch);
+    lv->prof_open = prev;
+    if (used) {
+      lv->prof[id].push_back({b, e});
+      lv->prof_batch[id].push_back(batch);
+    } else {
+      (void)hipEventDestroy(b);
+      (void)hipEventDestroy(e);
+    }
   }
 };
+
+// Launch of a level's kernel: plain, or, inside an open ProfScope on that
+// level, with the scope's events as the kernel's start and end timestamps.
+#define PFSH_LAUNCH(lv, kernel, grid, block, shm, stream, ...)                            \
+  do {                                                                                    \
+    pfsh::ProfScope* ps_ = (lv)->prof_open;                                               \
+    if (ps_ && !ps_->used) {                                                              \
+      ps_->used = true;                                                                   \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, ps_->b, ps_->e, 0,          \
+                            __VA_ARGS__);                                                 \
+    } else {                                                                              \
+      hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                  \
+    }                                                                                     \
+  } while (0)
 
 // ------------------------------------------------------------- host tables
 void gauss_legendre(int nlat, std::vector<double>& mu, std::vector<double>& w);
