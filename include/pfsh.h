@@ -236,10 +236,11 @@ pfsh_status pfsh_fas_tau(const pfsh_level* fine, const pfsh_level* coarse, doubl
                          void* tau_c, int batch, void* stream);
 
 /* Kernel timing (diagnostic).  While enabled on a level, every launch of the
- * listed kernels made through that level is bracketed by HIP events recorded
- * on the launch stream.  pfsh_profile_read synchronizes on the recorded events
- * and returns the number of bracketed launches and the sum of their durations
- * in milliseconds since the last enable.  Enabling clears earlier records.
+ * listed kernels made through that level carries a pair of HIP events that
+ * take the kernel's own start and end timestamps (the launch gap before it is
+ * not counted).  pfsh_profile_read synchronizes on the recorded events and
+ * returns the number of timed launches and the sum of their durations in
+ * milliseconds since the last enable.  Enabling clears earlier records.
  * Not to be enabled while a stream is being captured into a graph. */
 typedef enum {
   PFSH_K_LEG_SYNTH = 0,   /* Legendre synthesis contraction (MFMA)        */
