@@ -533,6 +533,35 @@ def sweep_benchmark(torch, pfsh, inputs, reps=20, rounds=5):
     return out
 
 
+GOLDEN = os.path.join(HERE, "tests", "golden", "pfasst_t255_t127_16x8.npz")
+
+
+def oracle_golden_err(final, golden_path=GOLDEN):
+    """Error of a block's final fine last-node states [16, 3, K] against the
+    FP64 oracle's block on the same workload (tests/golden, written by
+    tests/golden/make_pfasst_t255.py from the oracle alone; a fixed sample of
+    spectral slots): per time step and variable max |got - ref| / max |ref| on
+    the sample (the mean-geopotential slot out of the denominator), the maximum
+    over steps.  None for another workload."""
+    if WORKLOAD != "pfasst_t255_t127_16slices" or not os.path.exists(golden_path):
+        return None
+    d = np.load(golden_path)
+    meta = d["meta"]
+    if (tuple(int(x) for x in meta[:10]) != FINE + COARSE + (N_TS, 8) or float(meta[10]) != DT
+            or int(meta[11]) != SEED):
+        return None
+    slots, ref = d["slots"], d["final"]
+    got = np.asarray(final)[:, :, slots]
+    out = np.zeros(3)
+    for n in range(ref.shape[0]):
+        for v in range(3):
+            den = np.abs(ref[n, v]).copy()
+            if v == 0:
+                den[slots == 0] = 0.0
+            out[v] = max(out[v], np.abs(got[n, v] - ref[n, v]).max() / den.max())
+    return [float(x) for x in out]
+
+
 def rel_err_slices(a, b):
     """The paper's normalized max-norm error per variable, each slice (time
     step, member) normalized by its own reference; the maximum over slices."""
@@ -749,6 +778,9 @@ def main():
                  "sht_tflops": sht / (r64["ms"] * 1e-3) / 1e12},
         "mixed_rel_err_vs_fp64": err,
         "mixed_ok": bool(max(err) <= 1e-6),
+        "rel_err_vs_oracle_block": None if args.n_pf != 8 else {
+            "reference": "FP64 oracle block, tests/golden/pfasst_t255_t127_16x8.npz (sampled slots)",
+            "fp64": oracle_golden_err(x64), "mixed": oracle_golden_err(xmx)},
         "mixed_without_fp64_iterations_rel_err": err_pure,
         "mixed_rel_err_per_iteration": err_iter,
         "mixed_without_fp64_iterations_rel_err_per_iteration": err_iter_pure,
