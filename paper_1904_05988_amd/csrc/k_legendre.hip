@@ -557,14 +557,6 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_rec(
   }
 }
 
-// Analysis, the items and column tiles of k_leg_anal shape 0 (one (m, p) and
-// 64 degrees = two recurrence chunks per workgroup, 4 waves of 2 x 2 blocks).
-// The rings are taken in slabs of SR (64 degrees x SR rings fill 64 KiB): the
-// workgroup generates the slab's operand (thread task = (ring, chunk)), then
-// every wave runs its blocks over the slab's k-blocks with the data operand
-// PF k-blocks ahead (FP32: two chains by k-block parity).  A k-block row of
-// the LDS tile is padded by one element so that the generating threads, which
-// run over rings, spread over the banks.
 // K loop of one wave's NR x (1 + C1) blocks with the A operand in LDS: the
 // lane's element of iteration it at a_lane[it * astep] (second row block 64
 // elements on), the data operand from global memory PF k-blocks ahead.  The
@@ -627,6 +619,14 @@ __device__ __forceinline__ void mma_loop_lds(const typename Op::R* a_lane, int a
   }
 }
 
+// Analysis, the items and column tiles of k_leg_anal shape 0 (one (m, p) and
+// 64 degrees = two recurrence chunks per workgroup, 4 waves of 2 x 2 blocks).
+// The rings are taken in slabs of SR (64 degrees x SR rings fill 64 KiB): the
+// workgroup generates the slab's operand (thread task = (ring, chunk)), then
+// every wave runs its blocks over the slab's k-blocks with the data operand
+// PF k-blocks ahead (FP32: two chains by k-block parity).  A k-block row of
+// the LDS tile is padded by one element so that the generating threads, which
+// run over rings, spread over the banks.
 template <class Op, int PF>
 __global__ __launch_bounds__(256) void k_leg_anal_rec(
     const double* __restrict__ seeds, const double* __restrict__ rec, const double* __restrict__ mu,
@@ -708,9 +708,9 @@ __global__ __launch_bounds__(256) void k_leg_anal_rec(
 // The same contractions with the whole operand block generated once per
 // workgroup and kept in LDS while the workgroup runs every column tile: the
 // recurrence then costs once per (order, ring block) or (order, degree tile)
-// instead of once per column tile.  Used when the block fits in LDS (T up to
-// 511 for the synthesis; the analysis tile of 64 degrees x all rings up to
-// T767 in FP32 and T255 in FP64); the kernels above serve the rest.
+// instead of once per column tile.  Used when the block fits in LDS (the
+// synthesis up to T511; the analysis tile of 64 degrees x all rings up to 608
+// northern rings in FP32 and 288 in FP64); the kernels above serve the rest.
 
 // Synthesis: workgroup = MC orders of one parity x one block of 16 NRB rings,
 // wave w the column of order m0 + w ([k-block][NRB row blocks][64 lanes],
@@ -820,9 +820,9 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_rec_cols(
   }
 }
 
-// Analysis: workgroup = one (m, p) and 64 degrees with all rings in LDS;
-// after the generation each wave runs its two degree blocks against every
-// fourth pair of column blocks.
+// Analysis: workgroup = one (m, p) and 64 degrees with all rings in LDS, NW
+// waves; after the generation each wave runs its two degree blocks against
+// every (NW / 2)-th pair of column blocks.
 template <class Op, int PF, int NW>
 __global__ __launch_bounds__(64 * NW) void k_leg_anal_rec_cols(
     const double* __restrict__ seeds, const double* __restrict__ rec, const double* __restrict__ mu,
