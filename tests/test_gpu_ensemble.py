@@ -12,13 +12,20 @@ properties that hold at any size, plus sampled oracle values:
     iterations;
   * the T511 RHS of a member state matches the oracle (FP64 level; F_E to
     1e-11, F_I to 1e-14) and the FP32 level stays within its transform
-    round-off of it."""
+    round-off of it;
+  * one T511 sweep of a member (FP64 level, batch 1, from the spread initial
+    guess) matches the oracle's sweep at every node: the T255 sweep's bounds
+    (states 1e-12, F_E 1e-11) scaled by the growth of the Laplacian factor
+    n(n+1)/a^2 from T255 to T511 (x4): it carries the kinetic-energy term that
+    dominates the round-off of the tendencies, and the states inherit that
+    error through dt Q F_E (measured at T511: F_E 2.3e-11, states 1.5e-12, in
+    the divergence)."""
 
 import numpy as np
 import pytest
 import torch
 
-from oracle import swe
+from oracle import sdc, swe
 from paper_1904_05988_amd import inputs, pfsh
 from tests._gpu import rel_err, to_dev, to_host
 
@@ -101,3 +108,21 @@ def test_t511_rhs_sampled_against_oracle(states):
     # divergence/curl and the Laplacian (measured 2.4e-5, 3.3e-5, 5.4e-5)
     err = rel_err(to_host(fe32)[0], rfe)
     assert np.all(err <= 1e-4), err
+
+
+def test_t511_sweep_against_oracle(states):
+    x = states[2]
+    ol = swe.Level(*FINE[:3])
+    rth, rfe, rfi = sdc.spread(ol, x, FINE[3])
+    rth, rfe, rfi = sdc.sweep(ol, sdc.SDC(FINE[3]), DT, rth, rfe, rfi)
+    gl = pfsh.Level(*FINE, max_batch=1)
+    th, fe, fi = gl.space_time(1), gl.space_time(1), gl.space_time(1)
+    e, i = gl.rhs(to_dev(x[None]))
+    th[:, 0], fe[:, 0], fi[:, 0] = to_dev(x[None]), e, i
+    gl.spread(th, fe, fi)
+    gl.sdc_sweep(DT, th, fe, fi)
+    gth, gfe = to_host(th)[0], to_host(fe)[0]
+    for n in range(FINE[3]):
+        assert np.all(rel_err(gth[n], rth[n]) <= 4e-12), (n, rel_err(gth[n], rth[n]))
+        assert np.all(rel_err(gfe[n], rfe[n]) <= 4e-11), (n, rel_err(gfe[n], rfe[n]))
+    gl.close()
