@@ -541,8 +541,8 @@ def oracle_golden_err(final, golden_path=GOLDEN):
     FP64 oracle's block on the same workload (tests/golden, written by
     tests/golden/make_pfasst_t255.py from the oracle alone; a fixed sample of
     spectral slots): per time step and variable max |got - ref| / max |ref| on
-    the sample (the mean-geopotential slot out of the denominator), the maximum
-    over steps.  None for another workload."""
+    the sample (the mean-geopotential slot out of both maxima, as in rel_err),
+    the maximum over steps.  None for another workload."""
     if WORKLOAD != "pfasst_t255_t127_16slices" or not os.path.exists(golden_path):
         return None
     d = np.load(golden_path)
@@ -556,9 +556,11 @@ def oracle_golden_err(final, golden_path=GOLDEN):
     for n in range(ref.shape[0]):
         for v in range(3):
             den = np.abs(ref[n, v]).copy()
+            diff = np.abs(got[n, v] - ref[n, v])
             if v == 0:
                 den[slots == 0] = 0.0
-            out[v] = max(out[v], np.abs(got[n, v] - ref[n, v]).max() / den.max())
+                diff[slots == 0] = 0.0
+            out[v] = max(out[v], diff.max() / den.max())
     return [float(x) for x in out]
 
 
