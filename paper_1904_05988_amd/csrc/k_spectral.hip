@@ -463,13 +463,13 @@ __device__ __forceinline__ void node_update(double* __restrict__ th, double* __r
 //  (b) node_update (node 1 also accumulates the old-iterate terms);
 //  (c) the synthesis operand of Theta^node (prep_fields), reading the new
 //      states of this order from LDS.
-// One workgroup of 256 threads per (pair of orders, pair of slices): order g
+// One workgroup of 512 threads per (pair of orders, pair of slices): order g
 // goes with order T + 1 - g, so that every workgroup holds T + 1 degrees per
 // slice (order 0 and, for even T + 1, order (T + 1) / 2 stand alone).  The
 // (slice, order, degree) items of (a)-(b) are spread over all threads, (c)
 // takes one (order, degree) per thread.
 template <class Op, int NN, int ND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NN <= 5 ? 4 : 1, ND > 1 ? 4 : 8)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NN <= 5 ? 4 : 1, ND > 1 ? 4 : 8)))
 void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
                                                    double* __restrict__ fi,
                                                    const double* __restrict__ tau,
@@ -1076,7 +1076,7 @@ static hipError_t sweep_step_nd(const pfsh_level* lv, int node, int asm_node, do
     (void)hipFuncSetAttribute((const void*)k_sweep_step<Op, NN, ND>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   // order pairs (g, L - g): order 0, L/2 - 1 or (L-1)/2 pairs, and order L/2 for even L
-  PFSH_LAUNCH(lv, (k_sweep_step<Op, NN, ND>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(256), shm,
+  PFSH_LAUNCH(lv, (k_sweep_step<Op, NN, ND>), dim3(lv->L / 2 + 1, (batch + 1) / 2), dim3(512), shm,
                      s, th, fe, fi, tau, lv->S, (const typename Op::R*)lv->Y, lv->X, lv->mp_d,
                      lv->T, lv->CBs, batch, node, asm_node, dt, sdc_of(lv), phys_of(lv),
                      SrcPtrs{src.th, src.fe, src.fi, src.stride, src.fe_pending});
