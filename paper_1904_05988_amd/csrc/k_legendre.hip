@@ -62,11 +62,38 @@ __device__ __forceinline__ void store_run(R* dst, const R* v) {
   }
 }
 
+// Store a staged output tile: NROWS rings from j0 (stage rows of 32 real
+// columns, SM = MC + 1 per column) x 16 complex columns from real column c0,
+// MC consecutive orders from m0, into the Fourier workspace (f4_index, MG =
+// MC).  One 16-byte store per thread with lanes over (order quarter, column,
+// ring): a wave writes the whole-field runs of four slices of one ring, 4 x 256
+// contiguous bytes (FP32 or FP64, 4 fields).
+template <typename R, int MC, int NROWS>
+__device__ __forceinline__ void store_f4_tile(R* __restrict__ F4, const R* stage, int j0, int c0,
+                                              int J, int ncols, int nf, int p, int m0, int Lp) {
+  static_assert(MC == f4_mg(sizeof(R)), "one synthesis workgroup holds one order group");
+  constexpr int SM = MC + 1, VPT = 16 / (2 * (int)sizeof(R)), NQ = MC / VPT;
+  for (int t = threadIdx.x; t < NROWS * 16 * NQ; t += blockDim.x) {
+    const int qq = t % NQ, cp = (t / NQ) & 15, r = t / (NQ * 16);
+    const int j = j0 + r, c = c0 + 2 * cp;
+    if (j >= J || c >= ncols) continue;
+    const int bf = c >> 1, f = bf % nf, b = bf / nf;
+    const R* re = stage + (r * 32 + 2 * cp) * SM + qq * VPT;
+    const R* im = re + SM;
+    R out[2 * VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+      out[2 * v] = re[v];
+      out[2 * v + 1] = im[v];
+    }
+    store_run<R, 2 * VPT>(F4 + 2 * f4_index(b, j, f, p, m0 + qq * VPT, J, nf, Lp, MC), out);
+  }
+}
+
 // One workgroup: MC consecutive orders m0..m0+MC-1 of one parity, a tile of
 // 32 rings x 32 columns; wave w computes order m0 + w (2x2 MFMA blocks).  The
-// waves then exchange their tiles through LDS so that every thread stores the
-// MC consecutive-m complex values of one (ring, field) as one contiguous run
-// (64 bytes) in the [slice][ring][field][parity][m] layout the ring stage reads.
+// waves then exchange their tiles through LDS, and the tile is stored in
+// whole-field runs of the MC orders (store_f4_tile) for the ring stage.
 template <class Op, int MC, int PF, int HS = 32>
 __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ tab,
                                                       const void* __restrict__ X,
@@ -122,22 +149,7 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth(const void* __restrict__ 
         stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] = (R)acc[blk][v];
     }
     __syncthreads();
-    // HS rows x 16 complex columns, MC complex values each
-    for (int t = threadIdx.x; t < HS * 16; t += 64 * MC) {
-      const int r = t >> 4, cp = t & 15;
-      const int j = rb0 * 16 + h * HS + r, c = cb0 * 16 + 2 * cp;
-      if (j >= J || c >= ncols) continue;
-      const int bf = c >> 1, f = bf % nf, b = bf / nf;
-      R out[2 * MC];
-      const R* re = stage + (r * 32 + 2 * cp) * SM;
-      const R* im = re + SM;
-#pragma unroll
-      for (int mi = 0; mi < MC; ++mi) {
-        out[2 * mi] = re[mi];
-        out[2 * mi + 1] = im[mi];
-      }
-      store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
-    }
+    store_f4_tile<R, MC, HS>(F4, stage, rb0 * 16 + h * HS, cb0 * 16, J, ncols, nf, p, m0, Lp);
   }
 }
 
@@ -189,22 +201,8 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_t4(const void* __restrict
             (R)acc[2 * qr + (blk >> 1)][2 * qc + (blk & 1)][v];
     }
     __syncthreads();
-    const int rq = (rb0 + 2 * qr) * 16, cq = (cb0 + 2 * qc) * 16;
-    for (int t = threadIdx.x; t < 32 * 16; t += 64 * MC) {
-      const int r = t >> 4, cp = t & 15;
-      const int j = rq + r, c = cq + 2 * cp;
-      if (j >= J || c >= ncols) continue;
-      const int bf = c >> 1, f = bf % nf, b = bf / nf;
-      R out[2 * MC];
-      const R* re = stage + (r * 32 + 2 * cp) * SM;
-      const R* im = re + SM;
-#pragma unroll
-      for (int mi = 0; mi < MC; ++mi) {
-        out[2 * mi] = re[mi];
-        out[2 * mi + 1] = im[mi];
-      }
-      store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
-    }
+    store_f4_tile<R, MC, 32>(F4, stage, (rb0 + 2 * qr) * 16, (cb0 + 2 * qc) * 16, J, ncols, nf, p,
+                             m0, Lp);
   }
 }
 
@@ -540,21 +538,7 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_rec(
     for (int v = 0; v < 4; ++v) stage[((rr + Op::row(lane, v)) * 32 + cc) * SM + wave] = (R)acc[blk][v];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < 32 * 16; t += 64 * MC) {
-    const int rw = t >> 4, cp = t & 15;
-    const int j = rb0 * 16 + rw, c = cb0 * 16 + 2 * cp;
-    if (j >= J || c >= ncols) continue;
-    const int bf = c >> 1, f = bf % nf, b = bf / nf;
-    R out[2 * MC];
-    const R* re = stage + (rw * 32 + 2 * cp) * SM;
-    const R* im = re + SM;
-#pragma unroll
-    for (int mi = 0; mi < MC; ++mi) {
-      out[2 * mi] = re[mi];
-      out[2 * mi + 1] = im[mi];
-    }
-    store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
-  }
+  store_f4_tile<R, MC, 32>(F4, stage, rb0 * 16, cb0 * 16, J, ncols, nf, p, m0, Lp);
 }
 
 // K loop of one wave's NR x (1 + C1) blocks with the A operand in LDS: the
@@ -801,21 +785,7 @@ __global__ __launch_bounds__(64 * MC) void k_leg_synth_rec_cols(
           stage[(Op::row(lane, v) * 32 + cc) * SM + wave] = (R)acc[2 * hb + cbk][v];
       }
       __syncthreads();
-      for (int t = threadIdx.x; t < 16 * 16; t += 64 * MC) {
-        const int rw = t >> 4, cp = t & 15;
-        const int j = rbk * RW + hb * 16 + rw, c = cb0 * 16 + 2 * cp;
-        if (j >= J || c >= ncols) continue;
-        const int bf = c >> 1, f = bf % nf, b = bf / nf;
-        R out[2 * MC];
-        const R* re = stage + (rw * 32 + 2 * cp) * SM;
-        const R* im = re + SM;
-#pragma unroll
-        for (int mi = 0; mi < MC; ++mi) {
-          out[2 * mi] = re[mi];
-          out[2 * mi + 1] = im[mi];
-        }
-        store_run<R, 2 * MC>(F4 + (((((size_t)b * J + j) * nf + f) * 2 + p) * Lp + m0) * 2, out);
-      }
+      store_f4_tile<R, MC, 16>(F4, stage, rbk * RW + hb * 16, cb0 * 16, J, ncols, nf, p, m0, Lp);
     }
   }
 }

@@ -364,11 +364,13 @@ __global__ __launch_bounds__(NT) void k_ring_rhs(const typename Op::R* __restric
 #pragma unroll
     for (int f = 0; f < 4; ++f) buf[f * SP + padded(t)] = {(R)0, (R)0};
   }
-  const cpx<R>* src = reinterpret_cast<const cpx<R>*>(F4) + ((size_t)b * J + j) * 4 * 2 * Lp;
-  for (int m = tid; m < L; m += NT) {
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-      load_pair<R>(buf + f * SP, N, m, src[(f * 2 + 0) * Lp + m], src[(f * 2 + 1) * Lp + m]);
+  // the (b, j) region of the Fourier workspace, parity 0 then parity 1, each
+  // [m / MG][field][m % MG]: consecutive threads read consecutive values
+  constexpr int MG = f4_mg(sizeof(R));
+  const cpx<R>* src = reinterpret_cast<const cpx<R>*>(F4) + f4_index(b, j, 0, 0, 0, J, 4, Lp, MG);
+  for (int i = tid; i < 4 * Lp; i += NT) {
+    const int mi = i % MG, f = (i / MG) & 3, m = (i / (4 * MG)) * MG + mi;
+    if (m < L) load_pair<R>(buf + f * SP, N, m, src[i], src[4 * Lp + i]);
   }
   __syncthreads();
   const double muj = mu[j];
@@ -436,7 +438,7 @@ __global__ __launch_bounds__(NT) void k_ring_rhs(const typename Op::R* __restric
   }
 }
 
-// scalar synthesis: F4 [0][j][nf][2][Lp] -> grid [nf][nlat][N]
+// scalar synthesis: Fourier workspace (slice 0, nf fields) -> grid [nf][nlat][N]
 template <class Op, int N>
 __global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __restrict__ F4,
                                                    double* __restrict__ grid,
@@ -455,8 +457,8 @@ __global__ __launch_bounds__(256) void k_ring_synth(const typename Op::R* __rest
   for (int i = tid; i < 4 * L; i += NT) {
     const int fl = i / L, m = i - fl * L, f = f0 + fl;
     if (f >= nf) continue;
-    const R* e = F4 + ((((size_t)j * nf + f) * 2 + 0) * Lp + m) * 2;
-    const R* o = F4 + ((((size_t)j * nf + f) * 2 + 1) * Lp + m) * 2;
+    const R* e = F4 + 2 * f4_index(0, j, f, 0, m, J, nf, Lp, f4_mg(sizeof(R)));
+    const R* o = F4 + 2 * f4_index(0, j, f, 1, m, J, nf, Lp, f4_mg(sizeof(R)));
     load_pair<R>(buf + fl * SP, N, m, cpx<R>{e[0], e[1]}, cpx<R>{o[0], o[1]});
   }
   __syncthreads();

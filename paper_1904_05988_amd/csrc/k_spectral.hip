@@ -659,7 +659,7 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = rb * 16 + Op::row(lane, v);
-        if (j < J) F4[((((size_t)b * J + j) * 4 + f) * 2 + p) * Lp * 2 + (size_t)m * 2 + (c & 1)] = (R)acc[v];
+        if (j < J) F4[2 * f4_index(b, j, f, p, m, J, 4, Lp, f4_mg(sizeof(R))) + (c & 1)] = (R)acc[v];
       }
     }
   }

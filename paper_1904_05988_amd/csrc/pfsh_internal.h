@@ -30,6 +30,20 @@ __host__ __device__ inline int ext_pos(int T, int m, int n) {
   return ext_off(T, m) + ((d & 1) ? npar(T, m, 0) : 0) + (d >> 1);
 }
 
+// Fourier workspace (the Legendre synthesis writes it, the ring stage reads
+// it): per slice b and northern ring j a region of 2 x Lp x nf complex values
+// in the transform type, ordered [parity][m / MG][field][m % MG], MG = 64 bytes
+// of complex values (8 FP32, 4 FP64).  A synthesis workgroup holds MG
+// consecutive orders of one parity, so the runs of all its fields are
+// adjacent and its stores fill whole cache lines; the ring stage reads the
+// region of its (b, j) front to back.  Lp is a multiple of 8.
+__host__ __device__ constexpr int f4_mg(int real_bytes) { return 32 / real_bytes; }
+__host__ __device__ inline size_t f4_index(int b, int j, int f, int p, int m, int J, int nf,
+                                           int Lp, int MG) {
+  return (((size_t)b * J + j) * 2 + p) * (size_t)Lp * nf + (size_t)(m / MG) * MG * nf +
+         (size_t)f * MG + (m % MG);
+}
+
 // MFMA operand blocks.  FP64/FP32 use 16x16x4 MFMA: a block is 16 (row or
 // column) x 4 (k) elements and lane l holds element (l % 16, l / 16).  BF16x3
 // uses 16x16x32 MFMA: a block is 16 x 32 and lane l holds elements
@@ -132,7 +146,7 @@ struct pfsh_level {
   double* eps_d = nullptr; // [Kx] eps_n^m of the extended layout
   // workspace
   void* X = nullptr;       // synthesis data operand
-  void* F4 = nullptr;      // Fourier coefficients [batch][J][nf][2][L] complex (transform type)
+  void* F4 = nullptr;      // Fourier coefficients, f4_index layout (transform type)
   void* G = nullptr;       // analysis data operand (16 x 4 blocks, transform real type)
   void* Y = nullptr;       // analysis result [batch*5][Kx] complex (transform accumulate type)
   double* S = nullptr;     // sweep pre-accumulation [batch][M][3][K] complex
