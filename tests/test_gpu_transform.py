@@ -28,6 +28,32 @@ def test_sh_synthesis_matches_oracle(T, nlat, nlon):
         assert np.abs(grid[f] - ref).max() <= 1e-13 * np.abs(ref).max(), f
 
 
+# FP32 bound: unit roundoff u = 2^-24; the coefficients and tables are rounded
+# once each, every product once, the Legendre sums (<= 17 terms per parity at
+# T31, two accumulation chains) and the 7 FFT stages add at most one rounding
+# per step, so ~30 u relative to the field's size covers the worst case
+# (measured on gfx950: 1.3-1.8e-7, about 3 u).
+FIELD_COUNT_TOL = {"fp64": 1e-13, "fp32": 2e-6}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nf", [1, 9, 12])
+def test_sh_synthesis_field_counts(nf, prec):
+    """Field counts that leave partial 16-column tiles and partial groups of
+    four fields in the ring stage, up to the level's limit (4 x max_batch), in
+    both Fourier-workspace order groups (4 FP64, 8 FP32 orders): every field
+    against the oracle."""
+    T, nlat, nlon = 31, 48, 96
+    gl, ol = level_pair(T, nlat, nlon, 3, max_batch=3, precision=prec)
+    rng = np.random.default_rng(200 + nf)
+    spec = rng.standard_normal((nf, gl.K)) + 1j * rng.standard_normal((nf, gl.K))
+    spec[:, : T + 1] = spec[:, : T + 1].real
+    grid = to_host(gl.sh_synthesis(to_dev(spec)))
+    for f in range(nf):
+        ref = sht.synthesis(ol.g, spec[f])
+        assert np.abs(grid[f] - ref).max() <= FIELD_COUNT_TOL[prec] * np.abs(ref).max(), f
+
+
 @pytest.mark.parametrize("T,nlat,nlon", GRIDS)
 def test_sh_analysis_matches_oracle_and_round_trips(T, nlat, nlon):
     gl, ol = level_pair(T, nlat, nlon, 3, max_batch=2)
