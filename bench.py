@@ -11,7 +11,8 @@ iteration stops after its fine sweep), then the fine collocation residual.
 "sweeps/s" counts batched fine sweeps (all 16 slices) per second.
 
 The headline block runs the transform stages of both levels in mixed
-precision (FP32 by default) and its last two iterations with FP64 levels; the same block in
+precision (FP32 by default) and its last two iterations with an FP64 fine level
+(the coarse level keeps the mixed precision); the same block in
 plain FP64 is timed next to it, and the states of the two are compared after
 every iteration (and against serial FP64 SDC on the same time steps, the
 collocation solution PFASST converges to).
@@ -282,8 +283,9 @@ def sht_roundtrip_benchmark(torch, pfsh, reps=20, rounds=5):
 
 def make_block(args, mixed, n64, pfsh, inputs, torch):
     """Levels, PFASST context, arrays and the block closure for one precision
-    recipe: the transforms of both levels in `mixed`, FP64 levels for the last
-    n64 iterations (--coarse-fp64: the coarse level FP64 throughout)."""
+    recipe: the transforms of both levels in `mixed`, an FP64 fine level for
+    the last n64 iterations (--coarse-fp64: the coarse level FP64 throughout;
+    --finish-coarse-fp64: FP64 on the coarse level too in those iterations)."""
     dev = torch.device("cuda", 0)
     Tf, nlf, nof, nnf = FINE
     Tc, nlc, noc, nnc = COARSE
@@ -300,6 +302,8 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
     thf, fef, fif = gfm.space_time(B), gfm.space_time(B), gfm.space_time(B)
     res = torch.empty((B, 3), dtype=torch.float64, device=dev)
     k_switch = args.n_pf - n64
+    # coarse level of the FP64 finishing iterations
+    gcf = gc if getattr(args, "finish_coarse_fp64", False) else gcm
     tuned = {}
     if not getattr(args, "no_tune", False):
         # the batches each level runs: fine sweeps of all slices (the wavefront
@@ -327,12 +331,12 @@ def make_block(args, mixed, n64, pfsh, inputs, torch):
         else:
             for k in range(args.n_pf):
                 if k == k_switch:
-                    pf.set_levels(gf64, gc)
+                    pf.set_levels(gf64, gcf)
                 pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
         gf64.residual(DT, thf, fef, fif, out=res)
 
     return dict(block=block, pf=pf, levels=(gfm, gc, gf64, gcm), arrays=(thf, fef, fif), res=res,
-                tuned=tuned)
+                tuned=tuned, finish_coarse=gcf)
 
 
 def run_gpu(args, mixed, n64, torch, pfsh, inputs, profile=False):
@@ -405,7 +409,7 @@ def run_states(args, mixed, n64, torch, pfsh, inputs):
     out = []
     for k in range(args.n_pf):
         if k == args.n_pf - n64:
-            pf.set_levels(gf64, gc)
+            pf.set_levels(gf64, ctx["finish_coarse"])
         pf.iterate(DT, thf, fef, fif, last=(k == args.n_pf - 1))
         out.append(thf[:, -1].cpu().numpy())
     pf.close()
@@ -674,6 +678,10 @@ def main():
                     help="keep the coarse level in FP64 during the mixed iterations too (by "
                          "default its transforms take the mixed precision until the first FP64 "
                          "iteration)")
+    ap.add_argument("--finish-coarse-fp64", action="store_true",
+                    help="switch the coarse level to FP64 as well for the last n64 iterations "
+                         "(by default it keeps the mixed precision: the block's difference to "
+                         "the FP64 block sits in the fine modes above the coarse truncation)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default transform-kernel variants (no autotuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -685,6 +693,10 @@ def main():
         args.n_pf = 8 if args.workload == "t255" else 4
     if args.n64 is None:
         args.n64 = 2 if args.workload == "t255" else 0
+    if args.schedule == "wavefront" and args.finish_coarse_fp64:
+        print("--finish-coarse-fp64 needs --schedule iterations (the wavefront run switches "
+              "the fine level only)", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (time slices are its batch axis); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)

@@ -96,21 +96,23 @@ def test_mixed_precision_sweep_error(t255_states, prec):
     assert np.all(after < worst), (prec, worst, after)
 
 
-@pytest.mark.parametrize("n64,coarse_mixed", [(2, True), (4, True), (2, False)])
-def test_pfasst_mixed_block_with_fp64_finish_within_1e6(n64, coarse_mixed):
+@pytest.mark.parametrize("n64,coarse_mixed,finish_coarse_fp64",
+                         [(2, True, False), (2, True, True), (4, True, True), (2, False, True)])
+def test_pfasst_mixed_block_with_fp64_finish_within_1e6(n64, coarse_mixed, finish_coarse_fp64):
     """PFASST(16, 5, 3, 8) at T255/T127 from seed 3: FP32 transforms on the
     fine level (and, with coarse_mixed, on the coarse level) for the first
-    iterations, FP64 fine and coarse levels for the last n64 (2 with FP32
-    coarse transforms is the benchmark's recipe); the block ends within 1e-6
-    of the FP64 block (per variable), closer than all-FP32.  The modes the
-    coarse level also carries (n <= 127) are pulled back to the FP64 iterate
-    by the FP64 iterations; the rounding left above the coarse truncation is
-    only carried along by the fine sweeps and the initial-condition chain,
-    which is where the rest of the difference sits."""
+    iterations, an FP64 fine level for the last n64, with the coarse level
+    FP64 there too (finish_coarse_fp64) or still mixed (the benchmark's recipe:
+    n64 = 2, FP32 coarse transforms throughout); the block ends within 1e-6 of
+    the FP64 block (per variable), closer than all-FP32.  The modes the coarse
+    level also carries (n <= 127) are pulled back to the FP64 iterate by the
+    FP64 iterations; the rounding left above the coarse truncation is only
+    carried along by the fine sweeps and the initial-condition chain, which is
+    where the rest of the difference sits."""
     fine, coarse = (255, 384, 768, 5), (127, 192, 384, 3)
     th0 = to_dev(inputs.seeded_state(255, 3)[None])
 
-    def block(prec, n64, cmix):
+    def block(prec, n64, cmix, cfin64):
         gfm = pfsh.Level(*fine, max_batch=16, precision=prec)
         gc64 = pfsh.Level(*coarse, max_batch=16)
         gcm = pfsh.Level(*coarse, max_batch=16, precision=prec) if cmix else gc64
@@ -120,14 +122,14 @@ def test_pfasst_mixed_block_with_fp64_finish_within_1e6(n64, coarse_mixed):
         pf.predict(60.0, th0, th, fe, fi)
         for k in range(8):
             if k == 8 - n64:
-                pf.set_levels(gf64, gc64)
+                pf.set_levels(gf64, gc64 if cfin64 else gcm)
             pf.iterate(60.0, th, fe, fi, last=(k == 7))
         pf.close()
         return to_host(th)[:, -1]
 
-    ref = block("fp64", 0, False)
-    got = block("fp32", n64, coarse_mixed)
-    pure = block("fp32", 0, coarse_mixed)
+    ref = block("fp64", 0, False, True)
+    got = block("fp32", n64, coarse_mixed, finish_coarse_fp64)
+    pure = block("fp32", 0, coarse_mixed, True)
     n = np.concatenate([np.arange(m, 256) for m in range(256)])
     err, err_low, err_pure = np.zeros(3), np.zeros(3), np.zeros(3)
     for s in range(16):
@@ -137,12 +139,18 @@ def test_pfasst_mixed_block_with_fp64_finish_within_1e6(n64, coarse_mixed):
         diff = got[s].copy()
         diff[:, n > 127] = ref[s][:, n > 127]
         err_low = np.maximum(err_low, rel_err(diff, ref[s]))
-    print("n64", n64, "coarse mixed", coarse_mixed, "err", err, "low modes", err_low, "all FP32", err_pure)
+    print("n64", n64, "coarse mixed", coarse_mixed, "coarse FP64 in the finish", finish_coarse_fp64,
+          "err", err, "low modes", err_low, "all FP32", err_pure)
     assert np.all(err <= 1e-6), err
     # low modes: each FP64 iteration pulls them further back (measured, seed 3:
     # divergence 1.6e-7 (FP64 coarse throughout) and 1.8e-7 (FP32 coarse in the
-    # mixed iterations) after two FP64 iterations, 5e-9 after four)
-    assert np.all(err_low <= (3e-7 if n64 == 2 else 1e-7)), err_low
+    # mixed iterations) after two FP64 iterations, 5e-9 after four).  With the
+    # coarse level left in FP32 for the FP64 iterations (the benchmark's
+    # recipe) the last coarse correction carries FP32 transform rounding into
+    # them: 2.7e-7 measured, bounded by 4e-7; the total error is unchanged
+    # (7.7e-7), the high modes dominate it.
+    low_bound = 1e-7 if n64 >= 4 else (3e-7 if finish_coarse_fp64 else 4e-7)
+    assert np.all(err_low <= low_bound), err_low
     assert np.all(err_low <= err), (err_low, err)
     assert err[2] < err_pure[2], (err, err_pure)
 

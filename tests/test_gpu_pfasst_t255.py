@@ -10,7 +10,8 @@ reference values (the paper's max-norm per variable):
   * the FP64 block after the predictor, after every iteration (fine last node,
     and node 0 after step D of iterations 1, 4, 7) and at the end: <= 1e-11;
   * the benchmark's mixed recipe (FP32 transforms on both levels, the last
-    two iterations on FP64 levels) at the end: <= 1e-6."""
+    two iterations on an FP64 fine level; also with the coarse level switched
+    to FP64 for them) at the end: <= 1e-6."""
 
 import os
 
@@ -52,11 +53,11 @@ def golden():
     return {k: d[k] for k in d.files}
 
 
-def _run(golden, fine_first, fine_last, n64, coarse_prec="fp64"):
+def _run(golden, fine_first, fine_last, n64, coarse_prec="fp64", finish_coarse_fp64=True):
     """The block as the benchmark runs it (iteration order, graphs off); the
-    levels switch to `fine_last` and an FP64 coarse level for the final n64
-    iterations.  Returns the sampled values at the points the golden file
-    stores."""
+    fine level switches to `fine_last` for the final n64 iterations, the
+    coarse level to FP64 as well when finish_coarse_fp64.  Returns the sampled
+    values at the points the golden file stores."""
     gc = pfsh.Level(127, 192, 384, 3, max_batch=16)
     gcm = gc if coarse_prec == "fp64" else pfsh.Level(127, 192, 384, 3, max_batch=16,
                                                        precision=coarse_prec)
@@ -68,7 +69,7 @@ def _run(golden, fine_first, fine_last, n64, coarse_prec="fp64"):
     out = {"pred": to_host(thf[:, -1])[..., s], "last": [], "first": []}
     for k in range(8):
         if k == 8 - n64:
-            pf.set_levels(fine_last, gc)
+            pf.set_levels(fine_last, gc if finish_coarse_fp64 else gcm)
         pf.iterate(60.0, thf, fef, fif, last=(k == 7))
         if k < 7:
             out["last"].append(to_host(thf[:, -1])[..., s])
@@ -93,10 +94,11 @@ def test_fp64_block_matches_oracle(golden):
         assert np.all(e <= 1e-11), (k, e)
 
 
-def test_mixed_recipe_matches_oracle(golden):
+@pytest.mark.parametrize("finish_coarse_fp64", [False, True])
+def test_mixed_recipe_matches_oracle(golden, finish_coarse_fp64):
     gf32 = pfsh.Level(255, 384, 768, 5, max_batch=16, precision="fp32")
     gf64 = pfsh.Level(255, 384, 768, 5, max_batch=16)
-    got = _run(golden, gf32, gf64, 2, "fp32")
+    got = _run(golden, gf32, gf64, 2, "fp32", finish_coarse_fp64)
     per_iter = [_err(got["last"][k], golden["last"][k]) for k in range(7)]
     final = _err(got["final"], golden["final"])
     print("mixed per iteration", [[f"{x:.2e}" for x in e] for e in per_iter], "final", final)
