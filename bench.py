@@ -781,7 +781,9 @@ def main():
                    "members": MEMBERS, "spectrum": f"n^-{POWER:g}", "dt_s": DT,
                    "n_pf": args.n_pf, "fp64_final_iterations": args.n64,
                    "schedule": args.schedule,
-                   "coarse_precision": "fp64" if args.coarse_fp64 else f"{args.mixed} then fp64",
+                   "coarse_precision": "fp64" if args.coarse_fp64 else (
+                       f"{args.mixed} then fp64" if args.finish_coarse_fp64 and args.n64 > 0
+                       else args.mixed),
                    "step": "one PFASST block: predictor + n_pf iterations, fine residual",
                    "seeds": list(SEEDS), "parallelism": "slices x members as batch, 1 GPU"},
         "roofline": roof,
