@@ -823,7 +823,13 @@ struct InterpArrays {
   const double* old[3];
   double* io[3];
 };
-__global__ void k_interp_add(InterpArrays arr, int Tc, int Tf, int nc, int nf, int batch, TMat pm) {
+// NCT, NFT: the node counts at compile time (0: the run-time nc, nf, up to 9),
+// so that the common (3, 5) pair keeps only the registers and loads it needs.
+template <int NCT, int NFT>
+__global__ void k_interp_add(InterpArrays arr, int Tc, int Tf, int nc_rt, int nf_rt, int batch,
+                             TMat pm) {
+  constexpr int MC = NCT ? NCT : 9, MF = NFT ? NFT : 9;
+  const int nc = NCT ? NCT : nc_rt, nf = NFT ? NFT : nf_rt;
   const double* __restrict__ nw = arr.nw[blockIdx.y];
   const double* __restrict__ old = arr.old[blockIdx.y];
   double* __restrict__ io = arr.io[blockIdx.y];
@@ -838,9 +844,9 @@ __global__ void k_interp_add(InterpArrays arr, int Tc, int Tf, int nc, int nf, i
     int m, n;
     slot_mn(Tc, kc, m, n);
     const int kf = spec_off(Tf, m) + n - m;
-    C2 dz[9];
+    C2 dz[MC];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
+    for (int j = 0; j < MC; ++j) {
       if (j < nc) {
         const size_t o = (((size_t)b * nc + j) * 3 + v) * Kc + kc;
         dz[j] = ld2(nw + 2 * o);
@@ -852,11 +858,11 @@ __global__ void k_interp_add(InterpArrays arr, int Tc, int Tf, int nc, int nf, i
       }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < MF; ++i) {
       if (i < nf) {
         double sx = 0, sy = 0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
+        for (int j = 0; j < MC; ++j) {
           if (j < nc) {
             const double c = pm.P[i * nc + j];
             if (c != 0.0) {
@@ -877,10 +883,13 @@ __global__ void k_interp_add(InterpArrays arr, int Tc, int Tf, int nc, int nf, i
 struct TauMat {
   double Pcf[81], Qf[81], Qc[81];
 };
+template <int NFT, int NCT>
 __global__ void k_fas_tau(const double* __restrict__ fef, const double* __restrict__ fif,
                           const double* __restrict__ fec, const double* __restrict__ fic,
-                          double* __restrict__ tau, int Tf, int Tc, int nf, int nc, int batch,
-                          double dt, TauMat tm) {
+                          double* __restrict__ tau, int Tf, int Tc, int nf_rt, int nc_rt,
+                          int batch, double dt, TauMat tm) {
+  constexpr int MF = NFT ? NFT : 9, MC = NCT ? NCT : 9;   // as k_interp_add
+  const int nf = NFT ? NFT : nf_rt, nc = NCT ? NCT : nc_rt;
   const int Kc = (Tc + 1) * (Tc + 2) / 2, Kf = (Tf + 1) * (Tf + 2) / 2;
   const long long tot = (long long)batch * 3 * Kc;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
@@ -892,11 +901,12 @@ __global__ void k_fas_tau(const double* __restrict__ fef, const double* __restri
     int m, n;
     slot_mn(Tc, kc, m, n);
     const int kf = spec_off(Tf, m) + n - m;
-    // node loops unrolled to the 9-node maximum: the per-node values stay in
-    // registers (runtime-indexed arrays would live in scratch memory)
-    C2 Ff[9], Fc[9];
+    // node loops unrolled to the node count (or the 9-node maximum): the
+    // per-node values stay in registers (runtime-indexed arrays would live in
+    // scratch memory)
+    C2 Ff[MF], Fc[MC];
 #pragma unroll
-    for (int l = 0; l < 9; ++l) {
+    for (int l = 0; l < MF; ++l) {
       if (l < nf) {
         const size_t o = (((size_t)b * nf + l) * 3 + v) * Kf + kf;
         const C2 e = ld2(fef + 2 * o), f = ld2(fif + 2 * o);
@@ -904,7 +914,7 @@ __global__ void k_fas_tau(const double* __restrict__ fef, const double* __restri
       }
     }
 #pragma unroll
-    for (int l = 0; l < 9; ++l) {
+    for (int l = 0; l < MC; ++l) {
       if (l < nc) {
         const size_t o = (((size_t)b * nc + l) * 3 + v) * Kc + kc;
         const C2 e = ld2(fec + 2 * o), f = ld2(fic + 2 * o);
@@ -912,17 +922,17 @@ __global__ void k_fas_tau(const double* __restrict__ fef, const double* __restri
       }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < MC; ++i) {
       if (i >= nc) continue;
       double fx = 0, fy = 0;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) {
+      for (int j = 0; j < MF; ++j) {
         if (j >= nf) continue;
         const double c = tm.Pcf[i * nf + j];
         if (c == 0.0) continue;
         double qx = 0, qy = 0;
 #pragma unroll
-        for (int l = 0; l < 9; ++l) {
+        for (int l = 0; l < MF; ++l) {
           if (l < nf) {
             qx += tm.Qf[j * nf + l] * Ff[l].x;
             qy += tm.Qf[j * nf + l] * Ff[l].y;
@@ -933,7 +943,7 @@ __global__ void k_fas_tau(const double* __restrict__ fef, const double* __restri
       }
       double cx = 0, cy = 0;
 #pragma unroll
-      for (int l = 0; l < 9; ++l) {
+      for (int l = 0; l < MC; ++l) {
         if (l < nc) {
           cx += tm.Qc[i * nc + l] * Fc[l].x;
           cy += tm.Qc[i * nc + l] * Fc[l].y;
@@ -1273,8 +1283,13 @@ hipError_t launch_interp_add3(const pfsh_level* c, const pfsh_level* f, int coun
     arr.io[i] = inout_f[i];
   }
   const long long work = (long long)batch * 3 * c->K;
-  hipLaunchKernelGGL(k_interp_add, dim3(nblocks(work, 256), count), dim3(256), 0, s, arr, c->T,
-                     f->T, c->nn, f->nn, batch, pm);
+  const dim3 grid(nblocks(work, 256), count);
+  if (c->nn == 3 && f->nn == 5)
+    hipLaunchKernelGGL((k_interp_add<3, 5>), grid, dim3(256), 0, s, arr, c->T, f->T, c->nn, f->nn,
+                       batch, pm);
+  else
+    hipLaunchKernelGGL((k_interp_add<0, 0>), grid, dim3(256), 0, s, arr, c->T, f->T, c->nn, f->nn,
+                       batch, pm);
   return hipGetLastError();
 }
 
@@ -1292,8 +1307,12 @@ hipError_t launch_fas_tau(const pfsh_level* f, const pfsh_level* c, double dt, c
   for (int i = 0; i < f->nn * f->nn; ++i) tm.Qf[i] = f->Q[i];
   for (int i = 0; i < c->nn * c->nn; ++i) tm.Qc[i] = c->Q[i];
   const long long work = (long long)batch * 3 * c->K;
-  hipLaunchKernelGGL(k_fas_tau, dim3(nblocks(work, 256)), dim3(256), 0, s, fe_f, fi_f, fe_c, fi_c,
-                     tau, f->T, c->T, f->nn, c->nn, batch, dt, tm);
+  if (f->nn == 5 && c->nn == 3)
+    hipLaunchKernelGGL((k_fas_tau<5, 3>), dim3(nblocks(work, 256)), dim3(256), 0, s, fe_f, fi_f,
+                       fe_c, fi_c, tau, f->T, c->T, f->nn, c->nn, batch, dt, tm);
+  else
+    hipLaunchKernelGGL((k_fas_tau<0, 0>), dim3(nblocks(work, 256)), dim3(256), 0, s, fe_f, fi_f,
+                       fe_c, fi_c, tau, f->T, c->T, f->nn, c->nn, batch, dt, tm);
   return hipGetLastError();
 }
 
