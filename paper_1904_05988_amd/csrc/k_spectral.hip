@@ -241,17 +241,23 @@ __device__ __forceinline__ void assemble_mode(const R* __restrict__ Yb, int Kx, 
   assemble_core(get, m, n, a, out);
 }
 
+// One workgroup per (pair of orders, slice): order g goes with order T + 1 - g
+// (as in k_sweep_step), so that every workgroup has about T + 2 modes.
 template <typename R>
-__global__ __launch_bounds__(128) void k_assemble(const R* __restrict__ Y, double* __restrict__ fe,
+__global__ __launch_bounds__(256) void k_assemble(const R* __restrict__ Y, double* __restrict__ fe,
                                                  long long fstride, int T, double a) {
-  const int m = blockIdx.x, b = blockIdx.y;
+  const int L = T + 1, g = blockIdx.x, b = blockIdx.y;
+  const int ma = g, mb = (g >= 1 && L - g > g) ? L - g : -1;
+  const int na = L - ma, nb = mb >= 0 ? L - mb : 0;
   const int K = (T + 1) * (T + 2) / 2, Kx = ext_off(T, T + 1);
-  const int eoff = ext_off(T, m), off = spec_off(T, m);
   const R* Yb = Y + (size_t)b * 5 * Kx * 2;
   double* F = fe + (size_t)b * fstride * 2;
-  for (int n = m + threadIdx.x; n <= T; n += blockDim.x) {
+  for (int t = threadIdx.x; t < na + nb; t += blockDim.x) {
+    const bool first = t < na;
+    const int m = first ? ma : mb, n = m + (first ? t : t - na);
     C2 o[3];
-    assemble_mode(Yb, Kx, eoff, m, n, T, a, o);
+    assemble_mode(Yb, Kx, ext_off(T, m), m, n, T, a, o);
+    const int off = spec_off(T, m);
     for (int v = 0; v < 3; ++v) st2(F + 2 * ((size_t)v * K + off + n - m), o[v]);
   }
 }
@@ -1047,12 +1053,13 @@ hipError_t launch_unpack_scalar(const pfsh_level* lv, double* spec, int nfields,
 
 hipError_t launch_assemble(const pfsh_level* lv, double* f_expl, long long fstride, int batch,
                            hipStream_t s) {
-  dim3 grid(lv->L, batch);
+  // order pairs (g, L - g): order 0, L/2 - 1 or (L-1)/2 pairs, and order L/2 for even L
+  dim3 grid(lv->L / 2 + 1, batch);
   if (lv->op == OP_F64)
-    PFSH_LAUNCH(lv, k_assemble<double>, grid, dim3(128), 0, s, (const double*)lv->Y, f_expl,
+    PFSH_LAUNCH(lv, k_assemble<double>, grid, dim3(256), 0, s, (const double*)lv->Y, f_expl,
                        fstride, lv->T, lv->d.radius);
   else
-    PFSH_LAUNCH(lv, k_assemble<float>, grid, dim3(128), 0, s, (const float*)lv->Y, f_expl,
+    PFSH_LAUNCH(lv, k_assemble<float>, grid, dim3(256), 0, s, (const float*)lv->Y, f_expl,
                        fstride, lv->T, lv->d.radius);
   return hipGetLastError();
 }
