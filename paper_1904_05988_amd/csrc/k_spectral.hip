@@ -553,6 +553,17 @@ void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
 // bits.  FP64 and FP32 transform types.  16 waves per workgroup: the heaviest
 // orders (m near 0) have up to ~2 x (T/32) MFMA blocks per contraction, which
 // then run side by side instead of in rounds of one K chain after another.
+// Workgroup -> order for the fused node.  Workgroups are dealt to the 8 XCDs in
+// turn (workgroup b to XCD b mod 8); this bijection gives each XCD a range of
+// consecutive orders, so that the runs of the Fourier workspace (consecutive
+// orders of one field and ring) are written whole through one XCD's L2
+// instead of in pieces through several.
+__device__ __forceinline__ int xcd_order(int b, int n) {
+  constexpr int NX = 8;
+  const int x = b % NX, l = b / NX, q = n / NX, r = n % NX;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 template <class Op, int NN>
 __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, double* __restrict__ fe,
                                                    double* __restrict__ fi,
@@ -568,7 +579,7 @@ __global__ __launch_bounds__(1024) void k_node_fused(double* __restrict__ th, do
                                                    SdcMat sm, Phys ph, SrcPtrs src) {
   typedef typename Op::R R;
   constexpr int nn = NN, PF = 4;
-  const int m = blockIdx.x;
+  const int m = xcd_order(blockIdx.x, gridDim.x);   // gridDim.x = T + 1
   const int K = (T + 1) * (T + 2) / 2;
   const int off = spec_off(T, m), nm = T + 1 - m, nx = T + 2 - m;
   const int nsl = batch;                               // 1 or 2 slices
