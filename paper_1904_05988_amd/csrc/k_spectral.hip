@@ -554,13 +554,21 @@ void k_sweep_step(double* __restrict__ th, double* __restrict__ fe,
 // orders (m near 0) have up to ~2 x (T/32) MFMA blocks per contraction, which
 // then run side by side instead of in rounds of one K chain after another.
 // Workgroup -> order for the fused node.  Workgroups are dealt to the 8 XCDs in
-// turn (workgroup b to XCD b mod 8); this bijection gives each XCD a range of
-// consecutive orders, so that the runs of the Fourier workspace (consecutive
-// orders of one field and ring) are written whole through one XCD's L2
-// instead of in pieces through several.
+// turn (workgroup b to XCD b mod 8); this bijection gives each XCD whole groups
+// of 8 consecutive orders, so that the runs of the Fourier workspace (4 or 8
+// consecutive orders of one field and ring) are written whole through one
+// XCD's L2 instead of in pieces through several.  With a multiple of 128
+// orders, XCD x takes groups x and 15 - x of every 16 (a heavy and a light
+// group, as the orders' degree counts fall with m); else one range of
+// consecutive orders.
 __device__ __forceinline__ int xcd_order(int b, int n) {
   constexpr int NX = 8;
-  const int x = b % NX, l = b / NX, q = n / NX, r = n % NX;
+  const int x = b % NX, l = b / NX;
+  if (n % 128 == 0) {
+    const int s = l / 8, g = 16 * (s / 2) + ((s & 1) ? 15 - x : x);
+    return 8 * g + (l & 7);
+  }
+  const int q = n / NX, r = n % NX;
   return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
