@@ -92,9 +92,9 @@ def test_autotune_keeps_a_valid_choice_and_results():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 # T + 1 = 31 and 14 orders: the workgroup-to-order mapping with a remainder
-# over the 8 XCDs
+# over the 8 XCDs; 128 and 256 orders: its paired order groups
 @pytest.mark.parametrize("T,nlat,nlon,B", [(31, 48, 96, 1), (127, 192, 384, 1), (63, 96, 192, 2),
-                                           (30, 48, 96, 1), (13, 24, 48, 2)])
+                                           (30, 48, 96, 1), (13, 24, 48, 2), (255, 384, 768, 1)])
 def test_fused_small_batch_sweep_is_bitwise_equal(prec, T, nlat, nlon, B):
     """Batches of one or two slices sweep through the fused per-order node
     kernel by default; the separate kernels give the same bits, also with tau
